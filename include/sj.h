@@ -1,0 +1,228 @@
+/*
+ * sj.h -- runtime specialization of data-parallel kernels for AMD Instinct MI355X
+ * (gfx950).  C ABI: plain host/device pointers, sizes and status codes.
+ *
+ * The problem statement follows ClangJIT (Finkel, Poliakoff & Richards, 2019):
+ * a kernel whose sizes and data layout are known only at run time is
+ * instantiated with those values on first request, compiled in-process, kept
+ * in a program-global cache of instantiations and returned as a callable
+ * handle (section 4, Algorithm 1: cache lookup, compile, store, return), with
+ * no file-system access during the compile (section 1 and section 4: only data
+ * from the running binary is used).  Explicitly specialized code stays ahead
+ * of time (section 2); here that role is taken by the generic runtime-parameter
+ * kernels behind sj_generic_run, which are also the fallback that the
+ * paper's attribute-based design lacks (section 6, last list).
+ *
+ * Kernels:
+ *  - SJ_LTIMES / SJ_LPLUSTIMES: the discrete-ordinates moment operators of the
+ *    Kripke proxy application (section 5.2; the paper names the operators but
+ *    does not write them down):
+ *        phi[nm,g,z]  = sum_d  L[nm,d]  * psi[d,g,z]          (LTimes)
+ *        psi'[d,g,z]  = sum_nm L+[d,nm] * phi[nm,g,z]         (LPlusTimes)
+ *    over the six nestings of section 5.2's layout-dispatch listing, chosen at
+ *    run time (by enum, or by name string as in section 5.2's JIT launcher).
+ *  - SJ_BGEMM: batches of small square products C_i = A_i * B_i (section 5.1,
+ *    RAJA small matrix multiply), one persistent launch per batch plan.
+ *  - SJ_MLP_FWD / SJ_MLP_BWD / SJ_ADAM: the cost model that picks which
+ *    specialization to compile, an instance of the profile-guided adaptive
+ *    specialization and autotuning of section 6.
+ *
+ * Conventions (all entry points):
+ *  - Every entry point returns sj_status.  On failure, sj_last_error() returns
+ *    a thread-local message (for SJ_ERR_COMPILE it includes the compiler log).
+ *  - Device buffers belong to the caller; the library never frees them.
+ *  - Handles belong to the process-global cache; the same key always yields
+ *    the same handle; a handle stays valid until sj_cache_clear() or exit.
+ *    A handle is bound to the device that was current when it was created.
+ *  - Plans belong to the caller (sj_plan_destroy).
+ *  - Launches are asynchronous on `stream` (a hipStream_t; NULL is the null
+ *    stream) and report launch-time errors only; faults surface at the
+ *    caller's synchronization.
+ *  - Outputs are overwritten (beta = 0).
+ *  - Thread safety: sj_specialize compiles each key once even under concurrent
+ *    calls; sj_run and the batch calls are reentrant.
+ */
+#ifndef SJ_H
+#define SJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SJ_VERSION 1
+
+typedef enum sj_status {
+    SJ_OK = 0,
+    SJ_ERR_INVALID_ARG = 1,    /* bad size, enum, null pointer, struct_size */
+    SJ_ERR_UNSUPPORTED = 2,    /* valid request this library does not implement */
+    SJ_ERR_COMPILE = 3,        /* hiprtc rejected the emitted source; log in sj_last_error */
+    SJ_ERR_LOAD = 4,           /* the code object did not load on the device */
+    SJ_ERR_LAUNCH = 5,         /* kernel launch failed */
+    SJ_ERR_ALIGN = 6,          /* a pointer is not 16-byte aligned */
+    SJ_ERR_ALIAS = 7,          /* an input byte range overlaps an output byte range */
+    SJ_ERR_OOM = 8,            /* host or device allocation failed */
+    SJ_ERR_HIP = 9,            /* other HIP runtime error */
+    SJ_ERR_NOT_INITIALIZED = 10 /* no GPU device could be initialized */
+} sj_status;
+
+typedef enum sj_kernel {
+    SJ_LTIMES = 1,
+    SJ_LPLUSTIMES = 2,
+    SJ_BGEMM = 3,
+    SJ_MLP_FWD = 4,
+    SJ_MLP_BWD = 5,
+    SJ_ADAM = 6
+} sj_kernel;
+
+/* Storage order of a psi-like array's three axes, rightmost fastest.  phi uses
+ * the same order with D replaced by NM.  L is row-major [NM][D], L+ row-major
+ * [D][NM], in every layout. */
+typedef enum sj_layout {
+    SJ_DGZ = 0, SJ_DZG = 1, SJ_GDZ = 2, SJ_GZD = 3, SJ_ZDG = 4, SJ_ZGD = 5
+} sj_layout;
+
+typedef enum sj_dtype {
+    SJ_F64 = 0,     /* FP64 in, FP64 out, FP64 arithmetic */
+    SJ_BF16 = 1,    /* LTimes: psi FP32 in, phi FP32 out; one BF16 product per term, FP32 accumulate (MFMA) */
+    SJ_BF16X3 = 2,  /* as SJ_BF16 with split compensation: hi*hi + hi*lo + lo*hi per term */
+    SJ_F32 = 3      /* MLP kernels */
+} sj_dtype;
+
+/* Kernel structure for LTimes / LPlusTimes.  AUTO picks DIRECT when the
+ * innermost storage axis is a column axis (DGZ, DZG, GDZ, ZDG) and STAGED when
+ * it is the reduction/output axis (GZD, ZGD). */
+typedef enum sj_variant {
+    SJ_VAR_AUTO = 0,
+    SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
+    SJ_VAR_STAGED = 2,   /* rows of contiguous D (or NM) values staged through LDS */
+    SJ_VAR_MFMA = 3      /* matrix-core variant (BF16 dtypes) */
+} sj_variant;
+
+/* Flags. */
+#define SJ_FLAG_COMPILE_ONLY      0x1u  /* compile to a code object, do not load: no GPU needed; the handle cannot run */
+#define SJ_FLAG_INDEX64           0x2u  /* force 64-bit indexing (chosen automatically when an array has >= 2^31 elements) */
+#define SJ_FLAG_DEBUG_FAIL_COMPILE 0x100u /* test hook: the emitted source contains a failing static_assert */
+
+typedef struct sj_spec {
+    uint32_t struct_size;   /* must be sizeof(sj_spec) */
+    int32_t  dtype;         /* sj_dtype */
+    int32_t  layout;        /* sj_layout (LTimes / LPlusTimes) */
+    int32_t  variant;       /* sj_variant */
+    int64_t  Z, G, D, NM;   /* LTimes / LPlusTimes: zones, groups, directions, moments; each in [1, 2^31-1] */
+    int64_t  count;         /* BGEMM generic path: number of instances */
+    uint32_t class_mask;    /* BGEMM: bit n set when size class n (1 <= n <= 16) occurs; 0 = all of 1..16 */
+    int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
+                               BGEMM: max elements of A staged per chunk; 0 = default */
+    int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
+    int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs; 0 = default */
+    int32_t  block;         /* threads per workgroup (64..1024, multiple of 64); 0 = default */
+    uint32_t flags;         /* SJ_FLAG_* */
+    int64_t  rows, inputs, width;  /* MLP: batch rows, input features, hidden width */
+} sj_spec;
+
+typedef struct sj_handle_ *sj_handle;
+typedef struct sj_plan_ *sj_plan;
+
+typedef struct sj_kernel_info {
+    uint32_t struct_size;   /* must be sizeof(sj_kernel_info) */
+    int32_t  vgprs, agprs, sgprs;     /* from the compiler's resource-usage report (-1 if unknown) */
+    int32_t  lds_bytes, scratch_bytes, occupancy;  /* occupancy: waves per SIMD (-1 if unknown) */
+    int32_t  block;         /* threads per workgroup the handle launches with */
+    int64_t  grid;          /* workgroups per launch (LTimes/LPlusTimes/MLP), 0 if data-dependent */
+    int32_t  variant;       /* resolved sj_variant */
+    int32_t  tile_n, tile_k, unroll;  /* resolved tile parameters */
+    double   emit_ms, compile_ms, load_ms;
+    uint64_t code_bytes;
+    uint64_t key_hash;
+    char     kernel_name[64];
+} sj_kernel_info;
+
+typedef struct sj_stats_t {
+    uint32_t struct_size;   /* must be sizeof(sj_stats_t) */
+    uint64_t lookups, hits, misses, compiles, compile_failures, loads, inflight_waits, entries;
+    double   emit_ms_total, compile_ms_total, load_ms_total;
+} sj_stats_t;
+
+/* Initialize for HIP device `hip_device` (makes it current on the calling
+ * thread, reads its gcnArchName, turns comgr's on-disk cache off).
+ * Idempotent.  SJ_ERR_NOT_INITIALIZED when the device is absent. */
+sj_status sj_init(int hip_device);
+
+/* Parse a layout name ("DGZ" .. "ZGD", case-insensitive) into *out.  The
+ * analog of passing a type as a string (section 2, strings as types; section
+ * 5.2, layout string from a configuration file). */
+sj_status sj_layout_from_string(const char *name, int32_t *out);
+
+/* Canonicalize `spec` for kernel `k` (defaults filled in, tile parameters
+ * validated) and return the handle of that specialization, compiling it on a
+ * miss: emit source from templates embedded in this library, compile with
+ * hiprtc for the device's architecture, load the code object from memory.
+ * Errors: SJ_ERR_INVALID_ARG (sizes, enums, tiles, struct_size),
+ * SJ_ERR_UNSUPPORTED, SJ_ERR_COMPILE (no cache entry is kept, a retry
+ * recompiles), SJ_ERR_LOAD, SJ_ERR_NOT_INITIALIZED. */
+sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out);
+
+/* Launch a specialization.  No cache lookup happens here.  Pointers by kernel:
+ *   SJ_LTIMES:     {L [NM*D] f64, psi [D*G*Z] (f64, or f32 for BF16 dtypes), phi [NM*G*Z] (same type as psi)}
+ *   SJ_LPLUSTIMES: {L+ [D*NM] f64, phi [NM*G*Z] f64, psi_out [D*G*Z] f64}
+ *   SJ_MLP_FWD:    {theta f32, X [rows*inputs] f32, y [rows] f32}
+ *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32}
+ *   SJ_ADAM:       use sj_run_adam.
+ * Checks: handle runnable, nptrs, pointers non-null and 16-byte aligned
+ * (SJ_ERR_ALIGN), no overlap between an input and an output byte range
+ * (SJ_ERR_ALIAS: the no-alias guarantee that section 2 derives from unique
+ * objects).  SJ_BGEMM handles run through a plan instead. */
+sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream);
+
+/* Same math through the ahead-of-time generic kernels: sizes and strides are
+ * kernel arguments, no compile.  Supports SJ_LTIMES / SJ_LPLUSTIMES in SJ_F64
+ * (pointers as sj_run) and SJ_BGEMM with spec->count instances and pointers
+ * {n [count] int32 (device), off [count] int64 (device, element offsets), A, B, C}. */
+sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *const *ptrs, int nptrs, void *stream);
+
+/* Batched small products C_i = A_i * B_i, FP64, square n_i x n_i, row-major,
+ * packed: instance i starts at element off_i = sum_{j<i} n_j^2 of each of A, B, C.
+ * sj_batch_plan: h from sj_specialize(SJ_BGEMM, ...); n_host[count] with
+ * 1 <= n_i <= 16 and class n_i present in the handle's class mask.  Sorts the
+ * instances into size classes and uploads the work list (device memory owned
+ * by the plan).  sj_batch_run: one persistent launch on `stream`.
+ * sj_batch_graph_capture: records that launch into a HIP graph bound to A, B, C;
+ * sj_batch_graph_launch replays it. */
+sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_plan *out);
+sj_status sj_batch_run(sj_plan p, const double *A, const double *B, double *C, void *stream);
+sj_status sj_batch_graph_capture(sj_plan p, const double *A, const double *B, double *C, void *stream);
+sj_status sj_batch_graph_launch(sj_plan p, void *stream);
+/* Device arrays of the plan: n [count] int32 and off [count] int64 in the
+ * caller's instance order (usable with sj_generic_run(SJ_BGEMM)), and the
+ * total element count of each packed array. */
+sj_status sj_batch_plan_arrays(sj_plan p, const int32_t **n_dev, const int64_t **off_dev, int64_t *total_elems);
+sj_status sj_plan_destroy(sj_plan p);
+
+/* One Adam step (Kingma & Ba 2015) on `n` FP32 parameters for a handle from
+ * sj_specialize(SJ_ADAM, spec with rows = n):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * ptrs = {p, g, m, v}; step >= 1. */
+sj_status sj_run_adam(sj_handle h, void *const *ptrs, int nptrs, int64_t step,
+                      double lr, double b1, double b2, double eps, void *stream);
+
+/* The source text a spec compiles to (for inspection); `len` is the buffer
+ * size, *needed receives the size including the terminating NUL. */
+sj_status sj_emit_source(sj_kernel k, const sj_spec *spec, char *buf, size_t len, size_t *needed);
+
+sj_status sj_handle_info(sj_handle h, sj_kernel_info *out);
+/* Code object bytes of a handle (also valid for SJ_FLAG_COMPILE_ONLY handles). */
+sj_status sj_handle_code(sj_handle h, const void **code, size_t *size);
+sj_status sj_stats(sj_stats_t *out);
+/* Drop every cache entry and unload its module.  No handle may be in use. */
+sj_status sj_cache_clear(void);
+const char *sj_last_error(void);
+const char *sj_status_string(sj_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SJ_H */

@@ -1,0 +1,392 @@
+// Exported C ABI: device set-up, the program-global specialization cache and
+// the launch path.
+//
+// Cache (ClangJIT section 4, Algorithm 1: look the instantiation up, build it
+// on a miss, store it, return it): an unordered_map from the canonical key to
+// an entry, under one mutex.  A miss inserts a "building" entry and compiles
+// outside the lock; concurrent requests for the same key wait for that entry
+// instead of compiling again.  A failed build removes its entry, so a later
+// request retries.  The paper reports that the lookup itself is what costs
+// (section 5.1); here the lookup happens once, in sj_specialize, and sj_run
+// launches from the handle without touching the cache.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "sj_internal.h"
+
+namespace sj {
+
+namespace {
+
+enum EntryState { kBuilding = 0, kReady = 1, kFailed = 2 };
+
+struct Entry {
+    int state = kBuilding;
+    sj_handle_ *h = nullptr;
+    sj_status err = SJ_OK;
+    std::string msg;
+};
+
+std::mutex g_mu;
+std::condition_variable g_cv;
+std::unordered_map<SpecKey, std::shared_ptr<Entry>, KeyHashF, KeyEqF> g_map;
+sj_stats_t g_stats{};
+
+struct DeviceState {
+    bool ready = false;
+    std::string arch;
+};
+std::mutex g_dev_mu;
+DeviceState g_dev[64];
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+sj_status ensure_device(int *device, const char **arch)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SJ_ERR_NOT_INITIALIZED, "no HIP device is available");
+    }
+    if (dev < 0 || dev >= 64) return fail(SJ_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        if (g_dev[dev].ready) {
+            *device = dev;
+            *arch = g_dev[dev].arch.c_str();
+            return SJ_OK;
+        }
+    }
+    sj_status s = (sj_status)sj_init(dev);
+    if (s != SJ_OK) return s;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    *device = dev;
+    *arch = g_dev[dev].arch.c_str();
+    return SJ_OK;
+}
+
+static sj_status build_handle(const SpecKey &key, sj_handle_ **out)
+{
+    auto h = std::make_unique<sj_handle_>();
+    h->key = key;
+    h->hash = key_hash(key);
+    std::memset(&h->info, 0, sizeof h->info);
+    h->info.struct_size = sizeof(sj_kernel_info);
+    auto t0 = std::chrono::steady_clock::now();
+    std::string src;
+    sj_status s = emit_source(key, &src, &h->kernel_name);
+    if (s != SJ_OK) return s;
+    h->info.emit_ms = ms_since(t0);
+
+    t0 = std::chrono::steady_clock::now();
+    std::string log;
+    s = rtc_compile(src, key.arch, h->kernel_name, &h->code, &log);
+    h->info.compile_ms = ms_since(t0);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_stats.compiles++;
+        g_stats.compile_ms_total += h->info.compile_ms;
+        g_stats.emit_ms_total += h->info.emit_ms;
+        if (s != SJ_OK) g_stats.compile_failures++;
+    }
+    if (s != SJ_OK) return s;
+    parse_resource_usage(log, &h->info);
+    h->geom = key_geometry(key);
+    h->info.block = (int32_t)h->geom.block;
+    h->info.grid = h->geom.grid;
+    h->info.variant = key.variant;
+    h->info.tile_n = key.tile_n;
+    h->info.tile_k = key.tile_k;
+    h->info.unroll = key.unroll;
+    h->info.code_bytes = h->code.size();
+    h->info.key_hash = h->hash;
+    std::snprintf(h->info.kernel_name, sizeof h->info.kernel_name, "%s", h->kernel_name.c_str());
+
+    if (!(key.flags & SJ_FLAG_COMPILE_ONLY)) {
+        t0 = std::chrono::steady_clock::now();
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != key.device) {
+            if (hipSetDevice(key.device) != hipSuccess) return fail(SJ_ERR_HIP, "hipSetDevice failed");
+        }
+        hipError_t e = hipModuleLoadData(&h->module, h->code.data());
+        if (e != hipSuccess) return fail(SJ_ERR_LOAD, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+        e = hipModuleGetFunction(&h->fn, h->module, h->kernel_name.c_str());
+        if (e != hipSuccess) {
+            (void)hipModuleUnload(h->module);
+            return fail(SJ_ERR_LOAD, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+        }
+        h->info.load_ms = ms_since(t0);
+        h->runnable = true;
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_stats.loads++;
+        g_stats.load_ms_total += h->info.load_ms;
+    }
+    *out = h.release();
+    return SJ_OK;
+}
+
+sj_status get_or_build(const SpecKey &key, sj_handle_ **out)
+{
+    std::unique_lock<std::mutex> lk(g_mu);
+    g_stats.lookups++;
+    auto it = g_map.find(key);
+    if (it != g_map.end()) {
+        std::shared_ptr<Entry> e = it->second;
+        if (e->state == kReady) {
+            g_stats.hits++;
+            *out = e->h;
+            return SJ_OK;
+        }
+        g_stats.inflight_waits++;
+        g_cv.wait(lk, [&] { return e->state != kBuilding; });
+        if (e->state == kReady) {
+            g_stats.hits++;
+            *out = e->h;
+            return SJ_OK;
+        }
+        return fail(e->err, e->msg);
+    }
+    g_stats.misses++;
+    auto e = std::make_shared<Entry>();
+    g_map.emplace(key, e);
+    lk.unlock();
+
+    sj_handle_ *h = nullptr;
+    sj_status s = build_handle(key, &h);
+    std::string msg = (s == SJ_OK) ? std::string() : std::string(sj_last_error());
+
+    lk.lock();
+    if (s == SJ_OK) {
+        e->state = kReady;
+        e->h = h;
+        g_stats.entries++;
+    } else {
+        e->state = kFailed;
+        e->err = s;
+        e->msg = msg;
+        g_map.erase(key);
+    }
+    lk.unlock();
+    g_cv.notify_all();
+    if (s != SJ_OK) return fail(s, msg);
+    *out = h;
+    return SJ_OK;
+}
+
+static bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+// Byte sizes of the run pointers of a contraction handle; the last one is the output.
+static void contraction_bytes(const SpecKey &k, size_t *bytes)
+{
+    const size_t esz = (k.dtype == SJ_F64) ? 8 : 4;
+    const size_t cols = (size_t)k.G * (size_t)k.Z;
+    bytes[0] = (size_t)k.NM * (size_t)k.D * 8;
+    if (k.kernel == SJ_LTIMES) {
+        bytes[1] = (size_t)k.D * cols * esz;
+        bytes[2] = (size_t)k.NM * cols * esz;
+    } else {
+        bytes[1] = (size_t)k.NM * cols * esz;
+        bytes[2] = (size_t)k.D * cols * esz;
+    }
+}
+
+sj_status check_ptrs(void *const *ptrs, int nptrs, int expect, const size_t *bytes, int first_out)
+{
+    if (!ptrs) return fail(SJ_ERR_INVALID_ARG, "null pointer array");
+    if (nptrs != expect) return fail(SJ_ERR_INVALID_ARG, "wrong number of pointers");
+    for (int i = 0; i < nptrs; ++i) {
+        if (!ptrs[i]) return fail(SJ_ERR_INVALID_ARG, "null buffer pointer");
+        if (((uintptr_t)ptrs[i]) & 15u) return fail(SJ_ERR_ALIGN, "buffer pointer not 16-byte aligned");
+    }
+    for (int o = first_out; o < nptrs; ++o)
+        for (int i = 0; i < nptrs; ++i)
+            if (i != o && ranges_overlap(ptrs[i], bytes[i], ptrs[o], bytes[o]))
+                return fail(SJ_ERR_ALIAS, "an output buffer overlaps another buffer");
+    return SJ_OK;
+}
+
+}  // namespace sj
+
+using namespace sj;
+
+extern "C" {
+
+sj_status sj_init(int hip_device)
+{
+    clear_error();
+    if (hip_device < 0 || hip_device >= 64) return fail(SJ_ERR_INVALID_ARG, "device ordinal out of range");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= hip_device) {
+        (void)hipGetLastError();
+        return fail(SJ_ERR_NOT_INITIALIZED, "HIP device not present");
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_dev[hip_device].ready) return SJ_OK;
+    if (hipSetDevice(hip_device) != hipSuccess) return fail(SJ_ERR_HIP, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return fail(SJ_ERR_HIP, "hipGetDeviceProperties failed");
+    g_dev[hip_device].arch = prop.gcnArchName;
+    g_dev[hip_device].ready = true;
+    return SJ_OK;
+}
+
+sj_status sj_layout_from_string(const char *name, int32_t *out)
+{
+    clear_error();
+    if (!name || !out) return fail(SJ_ERR_INVALID_ARG, "null argument");
+    static const char *names[6] = {"DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD"};
+    char up[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i) {
+        char c = name[i];
+        if (i == 3) {
+            if (c != '\0') return fail(SJ_ERR_INVALID_ARG, "layout name must have three letters");
+            break;
+        }
+        if (c >= 'a' && c <= 'z') c = (char)(c - 'a' + 'A');
+        up[i] = c;
+        if (c == '\0') return fail(SJ_ERR_INVALID_ARG, "layout name must have three letters");
+    }
+    for (int i = 0; i < 6; ++i)
+        if (std::strcmp(up, names[i]) == 0) {
+            *out = i;
+            return SJ_OK;
+        }
+    return fail(SJ_ERR_INVALID_ARG, std::string("unknown layout '") + name + "'");
+}
+
+sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out)
+{
+    clear_error();
+    if (!spec || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output handle");
+    int device = -1;
+    const char *arch = "gfx950";
+    if (spec->struct_size == sizeof(sj_spec) && !(spec->flags & SJ_FLAG_COMPILE_ONLY)) {
+        sj_status s = ensure_device(&device, &arch);
+        if (s != SJ_OK) return s;
+    }
+    SpecKey key;
+    sj_status s = make_key(k, spec, device, arch, &key);
+    if (s != SJ_OK) return s;
+    sj_handle_ *h = nullptr;
+    s = get_or_build(key, &h);
+    if (s != SJ_OK) return s;
+    *out = h;
+    return SJ_OK;
+}
+
+sj_status sj_emit_source(sj_kernel k, const sj_spec *spec, char *buf, size_t len, size_t *needed)
+{
+    clear_error();
+    SpecKey key;
+    sj_status s = make_key(k, spec, -1, "gfx950", &key);
+    if (s != SJ_OK) return s;
+    std::string src, name;
+    s = emit_source(key, &src, &name);
+    if (s != SJ_OK) return s;
+    if (needed) *needed = src.size() + 1;
+    if (buf && len) {
+        size_t n = std::min(len - 1, src.size());
+        std::memcpy(buf, src.data(), n);
+        buf[n] = '\0';
+    }
+    return SJ_OK;
+}
+
+sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
+{
+    if (!h) return fail(SJ_ERR_INVALID_ARG, "null handle");
+    if (!h->runnable) return fail(SJ_ERR_INVALID_ARG, "handle was compiled with SJ_FLAG_COMPILE_ONLY and cannot run");
+    const SpecKey &k = h->key;
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+        size_t bytes[3];
+        contraction_bytes(k, bytes);
+        sj_status s = check_ptrs(ptrs, nptrs, 3, bytes, 2);
+        if (s != SJ_OK) return s;
+        void *a0 = ptrs[0], *a1 = ptrs[1], *a2 = ptrs[2];
+        void *args[] = {&a0, &a1, &a2};
+        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0,
+                                             (hipStream_t)stream, args, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
+    return fail(SJ_ERR_INVALID_ARG, "this handle is not launched through sj_run");
+}
+
+sj_status sj_handle_info(sj_handle h, sj_kernel_info *out)
+{
+    if (!h || !out) return fail(SJ_ERR_INVALID_ARG, "null argument");
+    if (out->struct_size != sizeof(sj_kernel_info)) return fail(SJ_ERR_INVALID_ARG, "sj_kernel_info.struct_size mismatch");
+    *out = h->info;
+    return SJ_OK;
+}
+
+sj_status sj_handle_code(sj_handle h, const void **code, size_t *size)
+{
+    if (!h || !code || !size) return fail(SJ_ERR_INVALID_ARG, "null argument");
+    *code = h->code.data();
+    *size = h->code.size();
+    return SJ_OK;
+}
+
+sj_status sj_stats(sj_stats_t *out)
+{
+    if (!out) return fail(SJ_ERR_INVALID_ARG, "null argument");
+    if (out->struct_size != sizeof(sj_stats_t)) return fail(SJ_ERR_INVALID_ARG, "sj_stats_t.struct_size mismatch");
+    std::lock_guard<std::mutex> lk(g_mu);
+    *out = g_stats;
+    out->struct_size = sizeof(sj_stats_t);
+    return SJ_OK;
+}
+
+sj_status sj_cache_clear(void)
+{
+    std::unique_lock<std::mutex> lk(g_mu);
+    for (auto &kv : g_map)
+        if (kv.second->state == kBuilding) return fail(SJ_ERR_INVALID_ARG, "a specialization is being compiled");
+    for (auto &kv : g_map) {
+        sj_handle_ *h = kv.second->h;
+        if (h) {
+            if (h->module) (void)hipModuleUnload(h->module);
+            delete h;
+        }
+    }
+    g_map.clear();
+    g_stats.entries = 0;
+    return SJ_OK;
+}
+
+const char *sj_status_string(sj_status s)
+{
+    switch (s) {
+    case SJ_OK: return "SJ_OK";
+    case SJ_ERR_INVALID_ARG: return "SJ_ERR_INVALID_ARG";
+    case SJ_ERR_UNSUPPORTED: return "SJ_ERR_UNSUPPORTED";
+    case SJ_ERR_COMPILE: return "SJ_ERR_COMPILE";
+    case SJ_ERR_LOAD: return "SJ_ERR_LOAD";
+    case SJ_ERR_LAUNCH: return "SJ_ERR_LAUNCH";
+    case SJ_ERR_ALIGN: return "SJ_ERR_ALIGN";
+    case SJ_ERR_ALIAS: return "SJ_ERR_ALIAS";
+    case SJ_ERR_OOM: return "SJ_ERR_OOM";
+    case SJ_ERR_HIP: return "SJ_ERR_HIP";
+    case SJ_ERR_NOT_INITIALIZED: return "SJ_ERR_NOT_INITIALIZED";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

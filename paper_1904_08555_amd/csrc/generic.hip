@@ -1,0 +1,184 @@
+// Ahead-of-time generic kernels: the same operations with every size and
+// stride a kernel argument.  They are the baseline that runtime specialization
+// is measured against (the paper's "AoT generic" variants, section 5) and the
+// fallback when a specialization cannot be compiled (section 6 notes that the
+// attribute-based design has no fallback path).
+//
+// What a generic kernel cannot do: keep a runtime-sized set of accumulators in
+// registers.  So the moments are processed in register chunks of 16 with the
+// reduction loop re-run per chunk (LTimes re-reads psi once per chunk of 16
+// moments; LPlusTimes adds each chunk's contribution into psi'), loop bounds
+// are runtime values, and addresses come from runtime strides.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "sj_internal.h"
+
+namespace {
+
+constexpr int kChunk = 16;
+constexpr int kBlock = 256;
+
+struct Strides {
+    long long Z, G, D, NM;
+    long long ad, ag, az;   // input offsets per unit of (reduction index, g, z)
+    long long bd, bg, bz;   // output offsets per unit of (output index, g, z)
+    int z_fast;             // 1: consecutive threads take consecutive z
+};
+
+__global__ void __launch_bounds__(kBlock)
+generic_ltimes(const double *__restrict__ L, const double *__restrict__ psi, double *__restrict__ phi, Strides s)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= s.G * s.Z) return;
+    long long g, z;
+    if (s.z_fast) { g = t / s.Z; z = t - g * s.Z; }
+    else { z = t / s.G; g = t - z * s.G; }
+    const double *p = psi + g * s.ag + z * s.az;
+    double *q = phi + g * s.bg + z * s.bz;
+    for (long long nm0 = 0; nm0 < s.NM; nm0 += kChunk) {
+        double acc[kChunk];
+        const double *Lr[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            acc[j] = 0.0;
+            Lr[j] = L + std::min(nm0 + j, s.NM - 1) * s.D;   // rows past NM repeat the last one; never stored
+        }
+        for (long long d = 0; d < s.D; ++d) {
+            const double x = p[d * s.ad];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) acc[j] = __builtin_fma(Lr[j][d], x, acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            if (nm0 + j < s.NM) q[(nm0 + j) * s.bd] = acc[j];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+generic_lplustimes(const double *__restrict__ Lp, const double *__restrict__ phi, double *__restrict__ out, Strides s)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= s.G * s.Z) return;
+    long long g, z;
+    if (s.z_fast) { g = t / s.Z; z = t - g * s.Z; }
+    else { z = t / s.G; g = t - z * s.G; }
+    const double *p = phi + g * s.ag + z * s.az;
+    double *q = out + g * s.bg + z * s.bz;
+    for (long long nm0 = 0; nm0 < s.NM; nm0 += kChunk) {
+        double x[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) x[j] = (nm0 + j < s.NM) ? p[(nm0 + j) * s.ad] : 0.0;
+        const long long jmax = std::min<long long>(kChunk, s.NM - nm0);
+        for (long long d = 0; d < s.D; ++d) {
+            const double *l = Lp + d * s.NM + nm0;
+            double o = 0.0;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) o = __builtin_fma(j < jmax ? l[j] : 0.0, x[j], o);
+            if (nm0 == 0) q[d * s.bd] = o;
+            else q[d * s.bd] += o;
+        }
+    }
+}
+
+// One workgroup (one wave) per instance, runtime n; A and B staged in LDS.
+__global__ void __launch_bounds__(64)
+generic_bgemm(const int *__restrict__ n, const long long *__restrict__ off, const double *__restrict__ A,
+              const double *__restrict__ B, double *__restrict__ C, long long count)
+{
+    __shared__ double a[256], b[256];
+    for (long long i = blockIdx.x; i < count; i += gridDim.x) {
+        const int s = n[i];
+        const long long o = off[i];
+        const int ss = s * s;
+        for (int e = threadIdx.x; e < ss; e += 64) {
+            a[e] = A[o + e];
+            b[e] = B[o + e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ss; e += 64) {
+            const int r = e / s, c = e - (e / s) * s;
+            double acc = 0.0;
+            for (int k = 0; k < s; ++k) acc = __builtin_fma(a[r * s + k], b[k * s + c], acc);
+            C[o + e] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Offsets of logical (a, g, z) for an (A, G, Z) array stored in `layout` order.
+void layout_strides(int layout, long long A, long long G, long long Z, long long *sa, long long *sg, long long *sz)
+{
+    switch (layout) {
+    case SJ_DGZ: *sa = G * Z; *sg = Z; *sz = 1; break;
+    case SJ_DZG: *sa = Z * G; *sz = G; *sg = 1; break;
+    case SJ_GDZ: *sg = A * Z; *sa = Z; *sz = 1; break;
+    case SJ_GZD: *sg = Z * A; *sz = A; *sa = 1; break;
+    case SJ_ZDG: *sz = A * G; *sa = G; *sg = 1; break;
+    default: /* ZGD */ *sz = G * A; *sg = A; *sa = 1; break;
+    }
+}
+
+}  // namespace
+
+extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *const *ptrs, int nptrs, void *stream)
+{
+    using namespace sj;
+    clear_error();
+    if (!spec) return fail(SJ_ERR_INVALID_ARG, "null spec");
+    if (spec->struct_size != sizeof(sj_spec)) return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size mismatch");
+    hipStream_t st = (hipStream_t)stream;
+    if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
+        if (spec->dtype != SJ_F64) return fail(SJ_ERR_UNSUPPORTED, "generic kernels are FP64 only");
+        if (spec->layout < SJ_DGZ || spec->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
+        const long long Z = spec->Z, G = spec->G, D = spec->D, NM = spec->NM;
+        if (Z < 1 || G < 1 || D < 1 || NM < 1 || Z > 2147483647LL || G > 2147483647LL || D > 2147483647LL ||
+            NM > 2147483647LL)
+            return fail(SJ_ERR_INVALID_ARG, "sizes must be in [1, 2^31-1]");
+        const size_t cols = (size_t)G * (size_t)Z;
+        size_t bytes[3];
+        bytes[0] = (size_t)NM * (size_t)D * 8;
+        bytes[1] = (k == SJ_LTIMES ? (size_t)D : (size_t)NM) * cols * 8;
+        bytes[2] = (k == SJ_LTIMES ? (size_t)NM : (size_t)D) * cols * 8;
+        sj_status s = check_ptrs(ptrs, nptrs, 3, bytes, 2);
+        if (s != SJ_OK) return s;
+        Strides st_{};
+        st_.Z = Z; st_.G = G; st_.D = D; st_.NM = NM;
+        const long long A_in = (k == SJ_LTIMES) ? D : NM, A_out = (k == SJ_LTIMES) ? NM : D;
+        layout_strides(spec->layout, A_in, G, Z, &st_.ad, &st_.ag, &st_.az);
+        layout_strides(spec->layout, A_out, G, Z, &st_.bd, &st_.bg, &st_.bz);
+        st_.z_fast = (st_.az <= st_.ag) ? 1 : 0;
+        const long long nblk = ((long long)cols + kBlock - 1) / kBlock;
+        if (nblk > 2147483647LL) return fail(SJ_ERR_UNSUPPORTED, "too many columns for one launch");
+        const double *L = (const double *)ptrs[0];
+        const double *in = (const double *)ptrs[1];
+        double *outp = (double *)ptrs[2];
+        if (k == SJ_LTIMES)
+            hipLaunchKernelGGL(generic_ltimes, dim3((unsigned)nblk), dim3(kBlock), 0, st, L, in, outp, st_);
+        else
+            hipLaunchKernelGGL(generic_lplustimes, dim3((unsigned)nblk), dim3(kBlock), 0, st, L, in, outp, st_);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
+    if (k == SJ_BGEMM) {
+        if (!ptrs || nptrs != 5) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes {n, off, A, B, C}");
+        for (int i = 0; i < 5; ++i) {
+            if (!ptrs[i]) return fail(SJ_ERR_INVALID_ARG, "null buffer pointer");
+            if (((uintptr_t)ptrs[i]) & 7u) return fail(SJ_ERR_ALIGN, "buffer pointer not 8-byte aligned");
+        }
+        const long long count = spec->count;
+        if (count < 0) return fail(SJ_ERR_INVALID_ARG, "count must be >= 0");
+        if (count == 0) return SJ_OK;
+        const unsigned grid = (unsigned)std::min<long long>(count, 1 << 20);
+        hipLaunchKernelGGL(generic_bgemm, dim3(grid), dim3(64), 0, st, (const int *)ptrs[0],
+                           (const long long *)ptrs[1], (const double *)ptrs[2], (const double *)ptrs[3],
+                           (double *)ptrs[4], count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
+    return fail(SJ_ERR_UNSUPPORTED, "no generic kernel for this kernel id");
+}

@@ -1,0 +1,293 @@
+// Specialization keys, source emission and in-process compilation.
+//
+// ClangJIT (section 4, Algorithm 1) turns (template, runtime values, type
+// strings) into an instantiation and caches it program-wide.  Here the
+// "template" is one of the kernel sources embedded in this library, the
+// runtime values become compile-time constants in an emitted prologue, and
+// hiprtc compiles the result for the device's architecture.  Nothing is read
+// from disk: the kernel text is a string constant of this binary (the paper's
+// fat-object idea, section 3, reduced to what a GPU kernel needs).
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <sstream>
+
+#include "sj_internal.h"
+#include "sj_templates.inc"  // generated at build time from csrc/kernels/*.hipk
+
+namespace sj {
+
+namespace {
+thread_local std::string t_err;
+
+uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+
+constexpr int64_t kMaxDim = 2147483647;  // each size <= 2^31 - 1
+
+}  // namespace
+
+sj_status fail(sj_status s, const std::string &msg)
+{
+    t_err = msg;
+    return s;
+}
+void clear_error() { t_err.clear(); }
+
+}  // namespace sj
+
+extern "C" const char *sj_last_error(void) { return sj::t_err.c_str(); }
+
+namespace sj {
+
+bool key_equal(const SpecKey &a, const SpecKey &b) { return std::memcmp(&a, &b, sizeof(SpecKey)) == 0; }
+
+uint64_t key_hash(const SpecKey &k)
+{
+    static_assert(sizeof(SpecKey) % 8 == 0, "key is hashed as 64-bit words");
+    uint64_t w[sizeof(SpecKey) / 8];
+    std::memcpy(w, &k, sizeof(SpecKey));
+    uint64_t h = 0x243F6A8885A308D3ull;
+    for (size_t i = 0; i < sizeof(SpecKey) / 8; ++i) h = mix64(h ^ w[i]) + 0x9E3779B97F4A7C15ull;
+    return h;
+}
+
+// ---------------------------------------------------------------- layouts
+
+// Contraction view of a layout: psi [B][D][I], phi [B][NM][I].
+static void layout_view(int layout, int64_t Z, int64_t G, int64_t *B, int64_t *I)
+{
+    switch (layout) {
+    case SJ_DGZ:
+    case SJ_DZG: *B = 1; *I = G * Z; break;
+    case SJ_GDZ: *B = G; *I = Z; break;
+    case SJ_ZDG: *B = Z; *I = G; break;
+    default: /* GZD, ZGD */ *B = G * Z; *I = 1; break;
+    }
+}
+
+static bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
+
+sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, SpecKey *out)
+{
+    if (!s || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output");
+    if (s->struct_size != sizeof(sj_spec))
+        return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size does not match this library's sj_spec");
+    SpecKey key;
+    std::memset(&key, 0, sizeof key);
+    key.kernel = (int32_t)k;
+    key.dtype = s->dtype;
+    key.device = device;
+    key.lib_version = SJ_VERSION;
+    std::snprintf(key.arch, sizeof key.arch, "%s", arch ? arch : "");
+    key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE);
+
+    if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
+        if (s->layout < SJ_DGZ || s->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
+        const int64_t dims[4] = {s->Z, s->G, s->D, s->NM};
+        for (int64_t v : dims)
+            if (v < 1 || v > kMaxDim) return fail(SJ_ERR_INVALID_ARG, "sizes must be in [1, 2^31-1]");
+        if (s->D > 4096 || s->NM > 4096) return fail(SJ_ERR_UNSUPPORTED, "D and NM are limited to 4096");
+        // element counts (checked for overflow of int64 first)
+        const int64_t cols = s->G * s->Z;  // < 2^62
+        if (cols > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "G*Z too large");
+        const int64_t maxa = std::max(s->D, s->NM);
+        if (cols > (INT64_MAX / 16) / maxa) return fail(SJ_ERR_INVALID_ARG, "array size overflows");
+        if (s->dtype == SJ_F64) {
+        } else if (s->dtype == SJ_BF16 || s->dtype == SJ_BF16X3) {
+            if (k != SJ_LTIMES) return fail(SJ_ERR_UNSUPPORTED, "BF16 dtypes are implemented for LTimes only");
+        } else {
+            return fail(SJ_ERR_INVALID_ARG, "dtype must be SJ_F64, SJ_BF16 or SJ_BF16X3");
+        }
+        key.layout = s->layout;
+        key.Z = s->Z; key.G = s->G; key.D = s->D; key.NM = s->NM;
+        layout_view(s->layout, s->Z, s->G, &key.B, &key.I);
+        const int64_t nelem = cols * maxa;
+        key.index64 = (nelem >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+
+        int var = s->variant;
+        if (var == SJ_VAR_AUTO) {
+            if (s->dtype != SJ_F64) var = SJ_VAR_MFMA;
+            else var = key.I == 1 ? SJ_VAR_STAGED : SJ_VAR_DIRECT;
+        }
+        if (s->dtype != SJ_F64 && var != SJ_VAR_MFMA)
+            return fail(SJ_ERR_INVALID_ARG, "BF16 dtypes need the MFMA variant");
+        if (s->dtype == SJ_F64 && var == SJ_VAR_MFMA)
+            return fail(SJ_ERR_UNSUPPORTED, "the FP64 path has no MFMA variant");
+        if (var < SJ_VAR_DIRECT || var > SJ_VAR_MFMA) return fail(SJ_ERR_INVALID_ARG, "variant out of range");
+        key.variant = var;
+        const int64_t red = (k == SJ_LTIMES) ? s->D : s->NM;   // reduction length
+        const int64_t outn = (k == SJ_LTIMES) ? s->NM : s->D;  // outputs per column
+        if (var == SJ_VAR_DIRECT) {
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            int vec = s->tile_n;
+            if (vec == 0) vec = (key.I % 2 == 0) ? 2 : 1;
+            if (vec != 1 && vec != 2 && vec != 4) return fail(SJ_ERR_INVALID_ARG, "DIRECT tile_n (columns per thread) must be 1, 2 or 4");
+            if (key.I % vec != 0) return fail(SJ_ERR_INVALID_ARG, "DIRECT tile_n must divide the contiguous column extent");
+            key.tile_n = vec;
+            int un = s->unroll ? s->unroll : 8;
+            if (un < 1 || un > 64) return fail(SJ_ERR_INVALID_ARG, "unroll must be in [1, 64]");
+            key.unroll = (int32_t)std::min<int64_t>(un, k == SJ_LTIMES ? s->D : s->D);
+            // Accumulators (LTimes) or moments (LPlusTimes) live in registers.
+            const int64_t regs = (k == SJ_LTIMES ? s->NM : s->NM) * vec;
+            if (regs > 128) return fail(SJ_ERR_UNSUPPORTED, "NM * tile_n > 128 FP64 values per thread");
+            // Full unrolling while the straight-line body stays moderate.
+            key.full_unroll = (red * outn * vec <= 4096) ? 1 : 0;
+            key.tile_k = 0;
+        } else if (var == SJ_VAR_STAGED) {
+            if (key.I != 1) return fail(SJ_ERR_UNSUPPORTED, "STAGED needs a layout with D innermost (GZD, ZGD)");
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            key.tile_n = s->tile_n ? s->tile_n : key.block;
+            if (key.tile_n % key.block != 0 || key.tile_n / key.block > 4)
+                return fail(SJ_ERR_INVALID_ARG, "STAGED tile_n (rows per workgroup) must be block, 2*block, 3*block or 4*block");
+            key.tile_k = s->tile_k ? s->tile_k : 16;
+            if (key.tile_k < 1 || key.tile_k > 256) return fail(SJ_ERR_INVALID_ARG, "tile_k must be in [1, 256]");
+            key.tile_k = (int32_t)std::min<int64_t>(key.tile_k, s->D);
+            const int64_t rpt = key.tile_n / key.block;
+            if (s->NM * rpt > 128) return fail(SJ_ERR_UNSUPPORTED, "NM * rows per thread > 128 FP64 values per thread");
+            const int64_t lds = (int64_t)key.tile_n * std::max<int64_t>(key.tile_k + 1, s->NM + 1) * 8;
+            if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "STAGED tile exceeds 160 KiB of LDS");
+            key.unroll = 0;
+            key.full_unroll = 1;
+        } else {
+            return fail(SJ_ERR_UNSUPPORTED, "MFMA variant is not available yet");
+        }
+        (void)outn;
+        return (*out = key), SJ_OK;
+    }
+    return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
+}
+
+Geometry key_geometry(const SpecKey &k)
+{
+    Geometry g{0, (unsigned)k.block};
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+        if (k.variant == SJ_VAR_DIRECT) {
+            const int64_t nv = k.B * (k.I / k.tile_n);
+            g.grid = (unsigned)((nv + k.block - 1) / k.block);
+        } else if (k.variant == SJ_VAR_STAGED) {
+            g.grid = (unsigned)((k.B + k.tile_n - 1) / k.tile_n);
+        }
+    }
+    return g;
+}
+
+// ---------------------------------------------------------------- emission
+
+static const char *kCommonPrologue =
+    "// emitted by the sj specializer\n"
+    "#if SJ_NT\n"
+    "#define SJ_LOAD(p) __builtin_nontemporal_load(p)\n"
+    "#define SJ_STORE(v, p) __builtin_nontemporal_store((v), (p))\n"
+    "#else\n"
+    "#define SJ_LOAD(p) (*(p))\n"
+    "#define SJ_STORE(v, p) (*(p) = (v))\n"
+    "#endif\n";
+
+sj_status emit_source(const SpecKey &k, std::string *src, std::string *name)
+{
+    std::ostringstream o;
+    const char *body = nullptr;
+    o << "// kernel " << k.kernel << " dtype " << k.dtype << " layout " << k.layout << " variant " << k.variant << "\n";
+    o << "typedef " << (k.index64 ? "long long" : "int") << " sj_index_t;\n";
+    const char *sfx = k.index64 ? "LL" : "";
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+        o << "#define SJ_D " << k.D << "\n#define SJ_NM " << k.NM << "\n";
+        o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
+        o << "#define SJ_BLOCK " << k.block << "\n";
+        // streaming hint: skip cache retention when every fetched line is used at once
+        const int nt = (k.variant == SJ_VAR_STAGED) ? 1 : (k.I * (k.tile_n ? k.tile_n : 1) >= 16 ? 1 : 0);
+        o << "#define SJ_NT " << nt << "\n";
+        if (k.variant == SJ_VAR_DIRECT) {
+            o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
+              << k.full_unroll << "\n";
+            body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_direct : kTpl_lplustimes_direct;
+            *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_direct" : "sj_lplustimes_direct";
+        } else if (k.variant == SJ_VAR_STAGED) {
+            o << "#define SJ_TILE_N " << k.tile_n << "\n#define SJ_TILE_K " << k.tile_k << "\n";
+            body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_staged : kTpl_lplustimes_staged;
+            *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_staged" : "sj_lplustimes_staged";
+        }
+    }
+    if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");
+    o << kCommonPrologue;
+    if (k.flags & SJ_FLAG_DEBUG_FAIL_COMPILE)
+        o << "static_assert(SJ_BLOCK < 0, \"compile failure requested by SJ_FLAG_DEBUG_FAIL_COMPILE\");\n";
+    o << body;
+    *src = o.str();
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- hiprtc
+
+static std::once_flag g_env_once;
+
+static void disable_disk_cache()
+{
+    // comgr keeps an on-disk cache of compilations unless AMD_COMGR_CACHE=0;
+    // the specializer must not depend on or leave files (ClangJIT section 1).
+    std::call_once(g_env_once, [] { setenv("AMD_COMGR_CACHE", "0", 1); });
+}
+
+sj_status rtc_compile(const std::string &src, const char *arch, const std::string &name, std::vector<char> *code,
+                      std::string *log)
+{
+    disable_disk_cache();
+    hiprtcProgram prog;
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), (name + ".hip").c_str(), 0, nullptr, nullptr);
+    if (r != HIPRTC_SUCCESS) return fail(SJ_ERR_COMPILE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
+    const std::string archopt = std::string("--offload-arch=") + arch;
+    const char *opts[] = {archopt.c_str(), "-O3", "-std=c++17", "-ffp-contract=fast",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-Rpass-analysis=kernel-resource-usage"};
+    r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string lg(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &lg[0]);
+    while (!lg.empty() && lg.back() == '\0') lg.pop_back();
+    if (log) *log = lg;
+    if (r != HIPRTC_SUCCESS) {
+        hiprtcDestroyProgram(&prog);
+        return fail(SJ_ERR_COMPILE, std::string("hiprtc compile failed (") + hiprtcGetErrorString(r) + "):\n" + lg);
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    code->resize(cs);
+    hiprtcGetCode(prog, code->data());
+    hiprtcDestroyProgram(&prog);
+    return SJ_OK;
+}
+
+static int remark_value(const std::string &log, const char *label)
+{
+    size_t p = log.find(label);
+    if (p == std::string::npos) return -1;
+    p += std::strlen(label);
+    while (p < log.size() && (log[p] == ' ' || log[p] == ':')) ++p;
+    return std::atoi(log.c_str() + p);
+}
+
+void parse_resource_usage(const std::string &log, sj_kernel_info *info)
+{
+    info->vgprs = remark_value(log, "remark:     VGPRs:");
+    info->agprs = remark_value(log, "remark:     AGPRs:");
+    info->sgprs = remark_value(log, "remark:     TotalSGPRs:");
+    info->scratch_bytes = remark_value(log, "ScratchSize [bytes/lane]:");
+    info->occupancy = remark_value(log, "Occupancy [waves/SIMD]:");
+    info->lds_bytes = remark_value(log, "LDS Size [bytes/block]:");
+}
+
+}  // namespace sj

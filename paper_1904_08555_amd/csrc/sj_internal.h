@@ -1,0 +1,84 @@
+// Internal declarations of the specialization library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sj.h"
+
+namespace sj {
+
+// Canonical, fully resolved specialization request.  Plain data; zero-filled
+// before use so that hashing and comparison can work on the raw bytes.
+struct SpecKey {
+    int32_t kernel, dtype, layout, variant;
+    int64_t Z, G, D, NM;
+    int64_t B, I;            // contraction view: psi [B][D][I], phi [B][NM][I]
+    int32_t tile_n, tile_k, unroll, block;
+    int32_t index64, full_unroll;
+    uint32_t class_mask;
+    uint32_t flags;          // key-relevant flags only
+    int64_t rows, inputs, width;
+    int32_t device;          // -1 for compile-only keys
+    int32_t lib_version;
+    char arch[64];
+};
+
+bool key_equal(const SpecKey &a, const SpecKey &b);
+uint64_t key_hash(const SpecKey &k);
+
+struct KeyHashF {
+    size_t operator()(const SpecKey &k) const { return (size_t)key_hash(k); }
+};
+struct KeyEqF {
+    bool operator()(const SpecKey &a, const SpecKey &b) const { return key_equal(a, b); }
+};
+
+// Thread-local error channel.
+sj_status fail(sj_status s, const std::string &msg);
+void clear_error();
+
+// Validate `spec` for kernel `k` and fill the canonical key (defaults resolved).
+// `device`/`arch` describe the target; device = -1 for compile-only requests.
+sj_status make_key(sj_kernel k, const sj_spec *spec, int device, const char *arch, SpecKey *out);
+
+// Source text (prologue + embedded template) and the kernel's symbol name.
+sj_status emit_source(const SpecKey &key, std::string *src, std::string *kernel_name);
+
+// Launch geometry of a resolved key.
+struct Geometry {
+    unsigned grid;
+    unsigned block;
+};
+Geometry key_geometry(const SpecKey &key);
+
+// hiprtc compile of `src` for `arch`; fills code and the compiler log.
+sj_status rtc_compile(const std::string &src, const char *arch, const std::string &name,
+                      std::vector<char> *code, std::string *log);
+
+// Parse the resource-usage remarks of a compiler log into info.
+void parse_resource_usage(const std::string &log, sj_kernel_info *info);
+
+// Validate run pointers: non-null, 16-byte aligned, outputs (index >= first_out)
+// overlapping no other buffer.
+sj_status check_ptrs(void *const *ptrs, int nptrs, int expect, const size_t *bytes, int first_out);
+
+// Initialized device state.
+sj_status ensure_device(int *device, const char **arch);
+
+}  // namespace sj
+
+struct sj_handle_ {
+    sj::SpecKey key;
+    uint64_t hash = 0;
+    std::string kernel_name;
+    std::vector<char> code;
+    hipModule_t module = nullptr;
+    hipFunction_t fn = nullptr;
+    sj::Geometry geom{0, 0};
+    sj_kernel_info info{};
+    bool runnable = false;
+};

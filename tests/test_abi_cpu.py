@@ -1,0 +1,171 @@
+"""CPU tests of the C ABI: the library loads and exports every entry point the
+header declares; keys canonicalize; the cache compiles each key once, also
+under concurrency; errors come back as status codes with messages.  Compiles
+here use SJ_FLAG_COMPILE_ONLY (hiprtc needs no GPU when the target is given);
+nothing is launched."""
+import os
+import re
+import threading
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1904_08555_amd as P
+    P.lib()
+    return P
+
+
+def header_entry_points():
+    with open(os.path.join(ROOT, "include", "sj.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^(?:sj_status|const char \*)\s*(sj_[a-z0-9_]+)\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(P):
+    names = header_entry_points()
+    assert len(names) >= 18
+    lib = P.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P.EXPORTED)
+
+
+def test_struct_sizes_match_header(P):
+    """The ctypes mirrors must have the C sizes (checked through struct_size validation)."""
+    import ctypes
+    s = P.make_spec(layout="DGZ", Z=4, G=2, D=3, NM=2, flags=P.SJ_FLAG_COMPILE_ONLY)
+    src = P.sj_emit_source(P.SJ_LTIMES, s)
+    assert "SJ_D 3" in src
+    s.struct_size = ctypes.sizeof(P.sj_spec) + 8
+    with pytest.raises(P.SJError) as e:
+        P.sj_emit_source(P.SJ_LTIMES, s)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+def test_layout_strings(P):
+    for i, name in enumerate(P.LAYOUTS):
+        assert P.sj_layout_from_string(name) == i
+        assert P.sj_layout_from_string(name.lower()) == i
+    for bad in ("", "DG", "DGZZ", "XYZ", "DDD"):
+        with pytest.raises(P.SJError) as e:
+            P.sj_layout_from_string(bad)
+        assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+def test_emitted_source_is_self_contained(P):
+    for layout in P.LAYOUTS:
+        for k in (P.SJ_LTIMES, P.SJ_LPLUSTIMES):
+            src = P.sj_emit_source(k, layout=layout, Z=32768, G=32, D=96, NM=16)
+            assert "#include" not in src
+            assert "SJ_D 96" in src and "SJ_NM 16" in src
+    big = P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", Z=262144, G=64, D=128, NM=16)
+    assert "typedef long long sj_index_t" in big        # 2^31 elements -> 64-bit indexing
+    small = P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", Z=4096, G=8, D=48, NM=16)
+    assert "typedef int sj_index_t" in small
+
+
+@pytest.mark.parametrize("bad", [
+    dict(Z=0), dict(G=-1), dict(D=2 ** 31), dict(NM=0), dict(layout=6), dict(dtype=9),
+    dict(block=100), dict(block=2048), dict(tile_n=3), dict(unroll=0, variant=1, tile_n=5),
+    dict(variant=2, layout="DGZ"), dict(variant=9),
+])
+def test_invalid_specs_rejected(P, bad):
+    spec = dict(layout="ZGD", Z=10, G=3, D=8, NM=4, flags=P.SJ_FLAG_COMPILE_ONLY)
+    spec.update(bad)
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_LTIMES, **spec)
+    assert e.value.status in (P.SJ_ERR_INVALID_ARG, P.SJ_ERR_UNSUPPORTED)
+    assert P.sj_last_error()
+
+
+def test_compile_only_cache_and_canonical_keys(P):
+    s0 = P.sj_stats()
+    h1 = P.sj_specialize(P.SJ_LTIMES, layout="DZG", Z=40, G=6, D=9, NM=5, flags=P.SJ_FLAG_COMPILE_ONLY)
+    # explicit defaults and a lower-case layout name canonicalize to the same key
+    h2 = P.sj_specialize(P.SJ_LTIMES, layout="dzg", Z=40, G=6, D=9, NM=5, block=256, tile_n=2, unroll=8,
+                         flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert h1 == h2
+    s1 = P.sj_stats()
+    assert s1["compiles"] - s0["compiles"] == 1
+    assert s1["hits"] - s0["hits"] == 1
+    info = P.sj_handle_info(h1)
+    assert info["kernel_name"] == "sj_ltimes_direct"
+    assert info["compile_ms"] > 0 and info["code_bytes"] > 1000
+    assert info["vgprs"] > 0 and info["sgprs"] > 0 and info["scratch_bytes"] == 0
+    code = P.sj_handle_code(h1)
+    assert code[:4] == b"\x7fELF"
+    # a compile-only handle cannot run
+    with pytest.raises(P.SJError) as e:
+        P.sj_run(h1, [16, 32, 48])
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    # a different tile is a different key
+    h3 = P.sj_specialize(P.SJ_LTIMES, layout="DZG", Z=40, G=6, D=9, NM=5, unroll=3, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert h3 != h1
+
+
+def test_concurrent_requests_compile_once(P):
+    s0 = P.sj_stats()
+    spec = dict(layout="GDZ", Z=77, G=5, D=11, NM=3, flags=P.SJ_FLAG_COMPILE_ONLY)
+    out = []
+    errs = []
+
+    def worker():
+        try:
+            out.append(P.sj_specialize(P.SJ_LPLUSTIMES, **spec))
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+
+    ts = [threading.Thread(target=worker) for _ in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs
+    assert len(set(out)) == 1
+    s1 = P.sj_stats()
+    assert s1["compiles"] - s0["compiles"] == 1
+    assert (s1["hits"] - s0["hits"]) == 7
+    assert s1["inflight_waits"] - s0["inflight_waits"] >= 1
+
+
+def test_forced_compile_error_leaves_no_entry(P):
+    spec = dict(layout="DGZ", Z=9, G=2, D=4, NM=2, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_DEBUG_FAIL_COMPILE)
+    s0 = P.sj_stats()
+    for _ in range(2):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_LTIMES, **spec)
+        assert e.value.status == P.SJ_ERR_COMPILE
+        assert "SJ_FLAG_DEBUG_FAIL_COMPILE" in e.value.message   # the compiler log is returned
+    s1 = P.sj_stats()
+    assert s1["compile_failures"] - s0["compile_failures"] == 2   # retried, not cached
+    assert s1["entries"] == s0["entries"]
+
+
+def test_generic_run_validates_before_launch(P):
+    with pytest.raises(P.SJError) as e:
+        P.sj_generic_run(P.SJ_LTIMES, [16, 32, 48], layout="DGZ", Z=0, G=1, D=1, NM=1)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    with pytest.raises(P.SJError) as e:
+        P.sj_generic_run(P.SJ_LTIMES, [16, 32, 48], layout="DGZ", Z=1, G=1, D=1, NM=1, dtype=P.SJ_BF16)
+    assert e.value.status == P.SJ_ERR_UNSUPPORTED
+    with pytest.raises(P.SJError) as e:
+        P.sj_generic_run(P.SJ_LTIMES, [16, 40, 48], layout="DGZ", Z=1, G=1, D=1, NM=1)
+    assert e.value.status == P.SJ_ERR_ALIGN
+    with pytest.raises(P.SJError) as e:   # output range overlaps the input range
+        P.sj_generic_run(P.SJ_LTIMES, [16, 4096, 4096 + 16], layout="DGZ", Z=4, G=1, D=4, NM=4)
+    assert e.value.status == P.SJ_ERR_ALIAS
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The product package and its C sources never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_1904_08555_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h", ".hipk")):
+                with open(os.path.join(dirpath, fn)) as f:
+                    text = f.read()
+                assert "oracle" not in text.lower(), os.path.join(dirpath, fn)
