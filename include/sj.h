@@ -92,13 +92,14 @@ typedef enum sj_dtype {
 } sj_dtype;
 
 /* Kernel structure for LTimes / LPlusTimes.  AUTO picks DIRECT when the
- * innermost storage axis is a column axis (DGZ, DZG, GDZ, ZDG) and STAGED when
- * it is the reduction/output axis (GZD, ZGD). */
+ * innermost storage axis is a column axis (DGZ, DZG, GDZ, ZDG) and the FP64
+ * matrix-core row kernel (MFMA) when it is D (GZD, ZGD); BF16 dtypes always
+ * use MFMA. */
 typedef enum sj_variant {
     SJ_VAR_AUTO = 0,
     SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
     SJ_VAR_STAGED = 2,   /* rows of contiguous D (or NM) values staged through LDS */
-    SJ_VAR_MFMA = 3      /* matrix-core variant (BF16 dtypes) */
+    SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 for layouts with D innermost */
 } sj_variant;
 
 /* Flags. */
@@ -120,6 +121,10 @@ typedef struct sj_spec {
     int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs; 0 = default */
     int32_t  block;         /* threads per workgroup (64..1024, multiple of 64); 0 = default */
     uint32_t flags;         /* SJ_FLAG_* */
+    int32_t  order;         /* DIRECT: 0 = default, 1 = every workgroup walks the reduction (LTimes) or
+                               output (LPlusTimes) rows in ascending order, 2 = each workgroup starts at a
+                               different row group (rotation), which spreads concurrent accesses over
+                               DRAM channels when rows are megabytes apart */
     int64_t  rows, inputs, width;  /* MLP: batch rows, input features, hidden width */
 } sj_spec;
 
@@ -208,6 +213,16 @@ sj_status sj_plan_destroy(sj_plan p);
  * ptrs = {p, g, m, v}; step >= 1. */
 sj_status sj_run_adam(sj_handle h, void *const *ptrs, int nptrs, int64_t step,
                       double lr, double b1, double b2, double eps, void *stream);
+
+/* Time a specialization (the measurement primitive of the autotuner): `warmup`
+ * untimed launches, then `reps` launches, each bracketed by HIP events on
+ * `stream`.  When flush_bytes > 0 the caller's scratch buffer `flush` is
+ * overwritten before every timed launch (outside the bracket) so the launch
+ * does not find its operands in L2 or the 256 MB last-level cache.
+ * times_ms[reps] receives each launch's duration; the stream is synchronized
+ * before returning.  Pointers as for sj_run. */
+sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int reps, void *flush,
+                      size_t flush_bytes, void *stream, float *times_ms);
 
 /* The source text a spec compiles to (for inspection); `len` is the buffer
  * size, *needed receives the size including the terminating NUL. */

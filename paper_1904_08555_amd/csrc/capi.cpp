@@ -328,6 +328,46 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
     return fail(SJ_ERR_INVALID_ARG, "this handle is not launched through sj_run");
 }
 
+sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int reps, void *flush,
+                      size_t flush_bytes, void *stream, float *times_ms)
+{
+    clear_error();
+    if (!h || !times_ms || reps < 1 || warmup < 0) return fail(SJ_ERR_INVALID_ARG, "bad timing arguments");
+    if (flush_bytes && !flush) return fail(SJ_ERR_INVALID_ARG, "flush_bytes > 0 needs a flush buffer");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < warmup; ++i) {
+        sj_status s = sj_run(h, ptrs, nptrs, stream);
+        if (s != SJ_OK) return s;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(SJ_ERR_HIP, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SJ_ERR_HIP, "hipEventCreate failed");
+    }
+    sj_status out = SJ_OK;
+    for (int i = 0; i < reps && out == SJ_OK; ++i) {
+        if (flush_bytes && hipMemsetAsync(flush, i & 0xff, flush_bytes, st) != hipSuccess) {
+            out = fail(SJ_ERR_HIP, "flush memset failed");
+            break;
+        }
+        (void)hipEventRecord(e0, st);
+        out = sj_run(h, ptrs, nptrs, stream);
+        (void)hipEventRecord(e1, st);
+        if (out != SJ_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            out = fail(SJ_ERR_HIP, "hipEventSynchronize failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        times_ms[i] = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return out;
+}
+
 sj_status sj_handle_info(sj_handle h, sj_kernel_info *out)
 {
     if (!h || !out) return fail(SJ_ERR_INVALID_ARG, "null argument");

@@ -118,12 +118,12 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         int var = s->variant;
         if (var == SJ_VAR_AUTO) {
             if (s->dtype != SJ_F64) var = SJ_VAR_MFMA;
-            else var = key.I == 1 ? SJ_VAR_STAGED : SJ_VAR_DIRECT;
+            else var = key.I == 1 ? SJ_VAR_MFMA : SJ_VAR_DIRECT;
         }
         if (s->dtype != SJ_F64 && var != SJ_VAR_MFMA)
             return fail(SJ_ERR_INVALID_ARG, "BF16 dtypes need the MFMA variant");
-        if (s->dtype == SJ_F64 && var == SJ_VAR_MFMA)
-            return fail(SJ_ERR_UNSUPPORTED, "the FP64 path has no MFMA variant");
+        if (s->dtype == SJ_F64 && var == SJ_VAR_MFMA && key.I != 1)
+            return fail(SJ_ERR_UNSUPPORTED, "the FP64 MFMA variant needs a layout with D innermost (GZD, ZGD)");
         if (var < SJ_VAR_DIRECT || var > SJ_VAR_MFMA) return fail(SJ_ERR_INVALID_ARG, "variant out of range");
         key.variant = var;
         const int64_t red = (k == SJ_LTIMES) ? s->D : s->NM;   // reduction length
@@ -132,7 +132,7 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
             int vec = s->tile_n;
-            if (vec == 0) vec = (key.I % 2 == 0) ? 2 : 1;
+            if (vec == 0) vec = (key.I % 2 == 0 && s->NM <= 16) ? 2 : 1;
             if (vec != 1 && vec != 2 && vec != 4) return fail(SJ_ERR_INVALID_ARG, "DIRECT tile_n (columns per thread) must be 1, 2 or 4");
             if (key.I % vec != 0) return fail(SJ_ERR_INVALID_ARG, "DIRECT tile_n must divide the contiguous column extent");
             key.tile_n = vec;
@@ -145,7 +145,16 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             // Full unrolling while the straight-line body stays moderate.
             key.full_unroll = (red * outn * vec <= 4096) ? 1 : 0;
             key.tile_k = 0;
+            // Rotation pays when consecutive rows are >= 1 MiB apart (measured on MI355X:
+            // 8 MiB row stride, 5.35 TB/s ascending vs 6.2 TB/s rotated).
+            int order = s->order;
+            if (order == 0) order = (key.I * 8 >= (int64_t(1) << 20)) ? 2 : 1;
+            if (order != 1 && order != 2) return fail(SJ_ERR_INVALID_ARG, "order must be 0, 1 or 2");
+            if ((k == SJ_LTIMES ? s->D : s->D) < 2 * key.unroll) order = 1;  // fewer than two row groups
+            key.order = order;
         } else if (var == SJ_VAR_STAGED) {
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            key.order = 1;
             if (key.I != 1) return fail(SJ_ERR_UNSUPPORTED, "STAGED needs a layout with D innermost (GZD, ZGD)");
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
@@ -161,8 +170,40 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "STAGED tile exceeds 160 KiB of LDS");
             key.unroll = 0;
             key.full_unroll = 1;
+        } else if (s->dtype == SJ_F64) {
+            // FP64 matrix-core row contraction (D innermost): tile_n = 16-row tiles per wave.
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            key.order = 1;
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            const int64_t ob = (outn + 15) / 16, kb = (red + 15) / 16;
+            int rt = s->tile_n;
+            if (rt == 0) rt = (2 * ob * 4 <= 96) ? 2 : 1;   // measured best on MI355X at D=96, NM=16
+            if (rt < 1 || rt > 8) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (16-row tiles per wave) must be in [1, 8]");
+            if (rt * ob * 4 > 96) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 96 FP64 values per lane");
+            key.tile_n = rt;
+            const int64_t nfrag = kb * 4 * ob;
+            key.unroll = nfrag <= 32 ? 1 : 0;       // W fragments in registers (1) or LDS (0)
+            if (!key.unroll && nfrag * 64 * 8 > 160 * 1024)
+                return fail(SJ_ERR_UNSUPPORTED, "MFMA weight fragments exceed 160 KiB of LDS");
+            key.tile_k = 16;
+            key.full_unroll = 1;
         } else {
-            return fail(SJ_ERR_UNSUPPORTED, "MFMA variant is not available yet");
+            // BF16 matrix-core LTimes, column axis contiguous: one 32-column tile per wave.
+            if (key.I == 1) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes needs a layout with a column axis innermost");
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            key.order = 1;
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            if (s->tile_n != 0 && s->tile_n != 1) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n must be 1");
+            key.tile_n = 1;
+            const int64_t frag_bytes = ((s->NM + 31) / 32) * ((s->D + 15) / 16) * 64 * 16;
+            if (frag_bytes * (s->dtype == SJ_BF16X3 ? 2 : 1) > 160 * 1024)
+                return fail(SJ_ERR_UNSUPPORTED, "BF16 weight fragments exceed 160 KiB of LDS");
+            if (s->D > 256) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes keeps a column's D values in registers: D <= 256");
+            key.tile_k = 16;
+            key.unroll = 0;
+            key.full_unroll = 1;
         }
         (void)outn;
         return (*out = key), SJ_OK;
@@ -179,6 +220,13 @@ Geometry key_geometry(const SpecKey &k)
             g.grid = (unsigned)((nv + k.block - 1) / k.block);
         } else if (k.variant == SJ_VAR_STAGED) {
             g.grid = (unsigned)((k.B + k.tile_n - 1) / k.tile_n);
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
+            const int64_t rows_per_block = (int64_t)(k.block / 64) * 16 * k.tile_n;
+            g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
+        } else if (k.variant == SJ_VAR_MFMA) {
+            const int64_t tiles = k.B * ((k.I + 31) / 32);
+            const int64_t waves = k.block / 64;
+            g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
         }
     }
     return g;
@@ -212,13 +260,24 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name)
         o << "#define SJ_NT " << nt << "\n";
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
-              << k.full_unroll << "\n";
+              << k.full_unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
             body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_direct : kTpl_lplustimes_direct;
             *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_direct" : "sj_lplustimes_direct";
         } else if (k.variant == SJ_VAR_STAGED) {
             o << "#define SJ_TILE_N " << k.tile_n << "\n#define SJ_TILE_K " << k.tile_k << "\n";
             body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_staged : kTpl_lplustimes_staged;
             *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_staged" : "sj_lplustimes_staged";
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
+            const bool lt = (k.kernel == SJ_LTIMES);
+            o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT "
+              << (lt ? k.NM : k.D) << "\n#define SJ_RT " << k.tile_n << "\n#define SJ_WREG " << k.unroll << "\n";
+            *name = lt ? "sj_ltimes_rows_mfma" : "sj_lplustimes_rows_mfma";
+            o << "#define SJ_KERNEL_NAME " << *name << "\n";
+            body = kTpl_rows_mfma64;
+        } else if (k.variant == SJ_VAR_MFMA) {
+            *name = (k.dtype == SJ_BF16X3) ? "sj_ltimes_bf16x3" : "sj_ltimes_bf16";
+            o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n#define SJ_KERNEL_NAME " << *name << "\n";
+            body = kTpl_ltimes_bf16;
         }
     }
     if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");

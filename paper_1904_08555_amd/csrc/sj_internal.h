@@ -19,6 +19,7 @@ struct SpecKey {
     int64_t B, I;            // contraction view: psi [B][D][I], phi [B][NM][I]
     int32_t tile_n, tile_k, unroll, block;
     int32_t index64, full_unroll;
+    int32_t order, pad0;
     uint32_t class_mask;
     uint32_t flags;          // key-relevant flags only
     int64_t rows, inputs, width;

@@ -55,7 +55,7 @@ SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 EXPORTED = (
     "sj_init", "sj_layout_from_string", "sj_specialize", "sj_run", "sj_generic_run", "sj_batch_plan",
     "sj_batch_run", "sj_batch_graph_capture", "sj_batch_graph_launch", "sj_batch_plan_arrays", "sj_plan_destroy",
-    "sj_run_adam", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
+    "sj_run_adam", "sj_time_run", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
     "sj_last_error", "sj_status_string",
 )
 
@@ -67,7 +67,7 @@ class sj_spec(ctypes.Structure):
         ("Z", ctypes.c_int64), ("G", ctypes.c_int64), ("D", ctypes.c_int64), ("NM", ctypes.c_int64),
         ("count", ctypes.c_int64), ("class_mask", ctypes.c_uint32),
         ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("unroll", ctypes.c_int32),
-        ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("block", ctypes.c_int32), ("flags", ctypes.c_uint32), ("order", ctypes.c_int32),
         ("rows", ctypes.c_int64), ("inputs", ctypes.c_int64), ("width", ctypes.c_int64),
     ]
 
@@ -132,6 +132,8 @@ def lib() -> ctypes.CDLL:
         "sj_batch_plan_arrays": [vp, P(vp), P(vp), P(i64)],
         "sj_plan_destroy": [vp],
         "sj_run_adam": [vp, P(vp), ctypes.c_int, i64, d, d, d, d, vp],
+        "sj_time_run": [vp, P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
+                        P(ctypes.c_float)],
         "sj_emit_source": [ctypes.c_int, P(sj_spec), ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)],
         "sj_handle_info": [vp, P(sj_kernel_info)],
         "sj_handle_code": [vp, P(vp), P(ctypes.c_size_t)],
@@ -254,6 +256,16 @@ def sj_generic_run(kernel: int, ptrs, spec: sj_spec | None = None, stream=None, 
         spec = make_spec(**kw)
     arr = _ptr_array(ptrs)
     _check(lib().sj_generic_run(int(kernel), ctypes.byref(spec), arr, len(ptrs), _stream(stream)))
+
+
+def sj_time_run(handle: Handle, ptrs, warmup: int = 2, reps: int = 10, flush=None, stream=None):
+    """Per-launch durations in ms (list of floats); see include/sj.h."""
+    arr = _ptr_array(ptrs)
+    out = (ctypes.c_float * reps)()
+    fbytes = 0 if flush is None else int(flush.numel() * flush.element_size())
+    _check(lib().sj_time_run(handle.ptr, arr, len(ptrs), int(warmup), int(reps), _addr(flush), fbytes,
+                             _stream(stream), out))
+    return list(out)
 
 
 def sj_emit_source(kernel: int, spec: sj_spec | None = None, **kw) -> str:

@@ -70,7 +70,8 @@ def test_emitted_source_is_self_contained(P):
 
 @pytest.mark.parametrize("bad", [
     dict(Z=0), dict(G=-1), dict(D=2 ** 31), dict(NM=0), dict(layout=6), dict(dtype=9),
-    dict(block=100), dict(block=2048), dict(tile_n=3), dict(unroll=0, variant=1, tile_n=5),
+    dict(block=100), dict(block=2048), dict(tile_n=3, variant=1, layout="DGZ"), dict(tile_n=9),
+    dict(unroll=0, variant=1, tile_n=5), dict(order=3, variant=1, layout="DGZ"), dict(order=2),
     dict(variant=2, layout="DGZ"), dict(variant=9),
 ])
 def test_invalid_specs_rejected(P, bad):

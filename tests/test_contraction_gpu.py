@@ -76,7 +76,9 @@ def test_ltimes_lplustimes_small(P, orc, layout, shape, generic):
 
 @pytest.mark.parametrize("layout", ["DGZ", "ZDG", "GZD"])
 @pytest.mark.parametrize("tile", [dict(tile_n=1, unroll=3, block=64), dict(tile_n=4, unroll=16, block=512),
-                                  dict(tile_n=2, unroll=1, block=1024)], ids=["t1u3b64", "t4u16b512", "t2u1b1024"])
+                                  dict(tile_n=2, unroll=1, block=1024), dict(tile_n=2, unroll=3, order=2),
+                                  dict(tile_n=1, unroll=2, block=64, order=2)],
+                         ids=["t1u3b64", "t4u16b512", "t2u1b1024", "t2u3rot", "t1u2b64rot"])
 def test_direct_tiles(P, orc, layout, tile):
     Z, G, D, NM = 96, 4, 13, 6
     L, Lp, psi, phi_in = contraction_inputs(5, layout, Z, G, D, NM)
@@ -256,3 +258,63 @@ def test_same_key_same_handle_and_stats(P):
     assert s1["compiles"] - s0["compiles"] <= 1 and s1["hits"] - s0["hits"] >= 1
     info = P.sj_handle_info(h1)
     assert info["kernel_name"] == "sj_ltimes_direct" and info["load_ms"] > 0 and info["scratch_bytes"] == 0
+
+
+MFMA_SHAPES = [(150, 3, 37, 9), (64, 4, 96, 16), (33, 1, 5, 3), (16, 1, 16, 16), (40, 2, 17, 20), (7, 3, 128, 64)]
+
+
+@pytest.mark.parametrize("layout", ["GZD", "ZGD"])
+@pytest.mark.parametrize("shape", MFMA_SHAPES, ids=lambda s: "Z%dG%dD%dNM%d" % s)
+@pytest.mark.parametrize("tile", [dict(), dict(tile_n=1, block=64), dict(tile_n=2, block=512), dict(tile_n=4, block=128)],
+                         ids=["default", "t1b64", "t2b512", "t4b128"])
+def test_mfma64_rows(P, orc, layout, shape, tile):
+    """FP64 matrix-core row kernels (D innermost): ragged rows, odd and
+    non-multiple-of-16 reduction lengths, output counts not multiple of 16,
+    weights in registers and in LDS (D=128, NM=64)."""
+    Z, G, D, NM = shape
+    L, Lp, psi, phi_in = contraction_inputs(8, layout, Z, G, D, NM)
+    try:
+        got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), variant=P.SJ_VAR_MFMA, **tile))
+    except P.SJError as e:
+        assert e.status == P.SJ_ERR_UNSUPPORTED, e
+        got = None
+    if got is not None:
+        ref = orc.ltimes(layout, Z, G, D, NM, L, psi)
+        scale = orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)
+        assert componentwise_err(got, ref, scale) <= TOL_F64
+    try:
+        got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), variant=P.SJ_VAR_MFMA, **tile))
+    except P.SJError as e:
+        assert e.status == P.SJ_ERR_UNSUPPORTED, e
+        return
+    ref2 = orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in)
+    scale2 = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)
+    assert componentwise_err(got2, ref2, scale2) <= TOL_F64
+
+
+def test_mfma64_full_size_sampled(P, orc):
+    Z, G, D, NM = 32768, 32, 96, 16
+    layout = "ZGD"
+    li = LAYOUTS.index(layout)
+    psi_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01, li, (D, G, Z))
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    Lp = gen.matrix_sym(0, gen.ARR_LPLUS, D, NM)
+    phi_d = run_ltimes(P, layout, Z, G, D, NM, dev(L), psi_d, variant=P.SJ_VAR_MFMA)
+    out_d = run_lplus(P, layout, Z, G, D, NM, dev(Lp), phi_d, variant=P.SJ_VAR_MFMA)
+    rng = np.random.default_rng(11)
+    g = rng.integers(0, G, 2048)
+    z = rng.integers(0, Z, 2048)
+    g[-1], z[-1] = G - 1, Z - 1
+    cols = gen.psi_columns(0, D, G, Z, g, z)
+    ref = orc.ltimes("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    scale = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    phi_log = gen.from_layout(host(phi_d), layout, NM, G, Z)
+    assert componentwise_err(phi_log[:, g, z], ref, scale) <= TOL_F64
+    phi_cols = phi_log[:, g, z]
+    ref2 = orc.lplustimes("DGZ", len(g), 1, D, NM, Lp, phi_cols).reshape(D, -1)
+    scale2 = orc.ltimes_absscale("DGZ", len(g), 1, NM, D, Lp, phi_cols).reshape(D, -1)
+    out_log = gen.from_layout(host(out_d), layout, D, G, Z)
+    assert componentwise_err(out_log[:, g, z], ref2, scale2) <= TOL_F64
+    del psi_d, phi_d, out_d
+    torch.cuda.empty_cache()
