@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU baseline sample")
     ap.add_argument("--tile", default="", help="override tile params, e.g. 'tile_n=2,unroll=8,block=256'")
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker"),
+                    help="moments: six nestings FP64 (default); batched: 200k small products; "
+                         "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
 
 
@@ -60,6 +63,23 @@ def main():
               "the contractions are independent per (g, z) column, so N GPUs would each run the one-GPU kernel "
               "on a zone shard.", file=sys.stderr)
         sys.exit(2)
+    import torch
+
+    import paper_1904_08555_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    P.sj_init(0)
+    if a.workload == "batched":
+        return bench_batched(a)
+    if a.workload == "bf16":
+        return bench_bf16(a)
+    if a.workload == "picker":
+        return bench_picker(a)
+    return bench_moments(a)
+
+
+def bench_moments(a):
     import numpy as np
     import torch
 
@@ -67,9 +87,6 @@ def main():
     import sj_inputs as gen
     from sj_inputs import device as gdev
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    P.sj_init(0)
     Z, G, D, NM = a.Z, a.G, a.D, a.NM
     layouts = [x for x in a.layouts.split(",") if x]
     tile = {}
@@ -242,6 +259,173 @@ def main():
         "generic": generic,
         "jit": jit,
         "cache_hit_us": round(hit_us, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def time_launches(fn, reps, stream):
+    """Median and mean duration (ms) of `reps` launches of fn, each bracketed by events."""
+    import torch
+    evs = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    ts = [x.elapsed_time(y) for x, y in evs]
+    return statistics.median(ts), statistics.mean(ts)
+
+
+def bench_batched(a):
+    """200,000 products C_i = A_i B_i, n_i ~ U{3..16}, A, B ~ N(0,1), FP64.
+    One step = one replay of the HIP graph holding the persistent launch."""
+    import numpy as np
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+
+    count = 200000
+    n = gen.batch_sizes(0, count)
+    off = gen.batch_offsets(n)
+    total = int(off[-1])
+    A_d = torch.from_numpy(gen.batch_normal(0, gen.ARR_A, total)).cuda()
+    B_d = torch.from_numpy(gen.batch_normal(0, gen.ARR_B, total)).cuda()
+    C_d = torch.empty(total, dtype=torch.float64, device="cuda")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")   # evicts L2 and the 256 MB LLC
+    tile = {}
+    for kv in filter(None, a.tile.split(",")):
+        k, v = kv.split("=")
+        tile[k] = int(v)
+    t0 = time.perf_counter()
+    h = P.sj_specialize(P.SJ_BGEMM, **tile)
+    jit_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    plan = P.sj_batch_plan(h, n)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    P.sj_batch_graph_capture(plan, A_d, B_d, C_d)
+    stream = torch.cuda.current_stream()
+    nbytes = 3 * total * 8
+    flops = 2 * int(np.sum(n.astype(np.int64) ** 3))
+    for _ in range(a.warmup):
+        P.sj_batch_graph_launch(plan)
+    torch.cuda.synchronize()
+    per = []
+    t_total = 0.0
+    for _ in range(a.steps):
+        flush.fill_(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        P.sj_batch_graph_launch(plan)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        per.append(e0.elapsed_time(e1))
+    med = statistics.median(per)
+    mean = statistics.mean(per)
+    n_dev, off_dev, _ = P.sj_batch_plan_arrays(plan)
+    gspec = P.make_spec(count=count)
+
+    def generic():
+        P.sj_generic_run(P.SJ_BGEMM, [n_dev, off_dev, A_d, B_d, C_d], gspec)
+    generic()
+    gmed, _ = time_launches(generic, max(3, a.steps // 2), stream)
+    info = P.sj_handle_info(h)
+    line = {
+        "metric": "batched small products GB/s (persistent per-class graph launch vs per-instance generic)",
+        "value": round(nbytes / (med * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(t_total * 1e3 / a.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64, seed 0)",
+        "config": {"workload": "200000 products, n ~ U{3..16}, A,B ~ N(0,1), FP64, packed row-major",
+                   "total_elements": total, "flops": flops},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (mean * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "sj_bgemm_persistent", "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes},
+        "graph_us_median": round(med * 1e3, 2), "generic_us": round(gmed * 1e3, 2),
+        "speedup_vs_generic": round(gmed / med, 3), "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
+        "kernel_info": {k: info[k] for k in ("vgprs", "sgprs", "occupancy", "lds_bytes", "scratch_bytes", "block")},
+    }
+    P.sj_plan_destroy(plan)
+    print(json.dumps(line), flush=True)
+
+
+def bench_bf16(a):
+    """LTimes, DGZ, Z=262144 G=64 D=128 NM=64: BF16 (psi FP32 in, phi FP32 out),
+    compensated BF16x3, and the FP64 path on the same values."""
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+    from sj_inputs import device as gdev
+
+    Z, G, D, NM = 262144, 64, 128, 64
+    L_d = torch.empty(NM * D, dtype=torch.float64, device="cuda")
+    gdev.fill(L_d, 0, gen.ARR_L, gdev.DIST_SYM)
+    psi32 = torch.empty(D * G * Z, dtype=torch.float32, device="cuda")
+    gdev.fill(psi32, 0, gen.ARR_PSI, gdev.DIST_U01_24, 0, (D, G, Z))
+    phi32 = torch.empty(NM * G * Z, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    b32 = (D + NM) * G * Z * 4 + NM * D * 8
+    for name, dt in (("bf16", P.SJ_BF16), ("bf16x3", P.SJ_BF16X3)):
+        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt)
+        t = P.sj_time_run(h, [L_d, psi32, phi32], warmup=a.warmup, reps=a.steps)
+        ms = statistics.median(t)
+        info = P.sj_handle_info(h)
+        res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
+                         frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         vgprs=info["vgprs"], occupancy=info["occupancy"])
+    del phi32
+    psi64 = psi32.to(torch.float64)
+    del psi32
+    phi64 = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
+    h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM)
+    t = P.sj_time_run(h, [L_d, psi64, phi64], warmup=a.warmup, reps=a.steps)
+    ms = statistics.median(t)
+    b64 = (D + NM) * G * Z * 8 + NM * D * 8
+    flops = 2 * D * NM * G * Z
+    res["f64"] = dict(ms=round(ms, 4), gbs=round(b64 / (ms * 1e-3) / 1e9, 1),
+                      tflops=round(flops / (ms * 1e-3) / 1e12, 2), frac_fp64_peak=round(flops / (ms * 1e-3) / 78.6e12, 4))
+    best = res["bf16x3"]
+    line = {
+        "metric": "LTimes BF16 (split-compensated) GB/s at Z=262144 G=64 D=128 NM=64",
+        "value": best["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3 (fp32 accumulate)", "data": "synthetic (SplitMix64, seed 0)",
+        "config": {"workload": "LTimes DGZ Z=262144 G=64 D=128 NM=64, psi FP32 in, phi FP32 out"},
+        "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": best["frac"], "traffic": None, "kernel": "sj_ltimes_bf16x3", "bytes_per_launch": b32},
+        "modes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_picker(a):
+    """Learned picker: 500 shapes x 4 random candidates = 2000 timed training
+    configurations, 200 held-out shapes tuned exhaustively; regret of the pick
+    against the tuner's best and speedup over the untuned default."""
+    import os
+
+    from paper_1904_08555_amd import picker
+
+    t0 = time.perf_counter()
+    res, pk = picker.run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=12, epochs=300,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    os.makedirs("gpurun_out", exist_ok=True)
+    pk.save("gpurun_out/picker_weights.json")
+    line = {
+        "metric": "picker regret vs exhaustive autotuner (mean over held-out shapes)",
+        "value": res["regret_mean"], "unit": "fraction", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 model; f64 and bf16x3 kernels", "data": "synthetic (SplitMix64 + timings gathered here)",
+        "config": {"workload": "picker: 2000 timed training configs, 200 held-out shapes; Z=k^3 k in 8..64, "
+                               "G in 8..128, D in 16..256 step 8, NM in {4,9,16,36,64}, dtype in {f64, bf16x3}"},
+        "roofline": None, "cpu_baseline": None, "picker": res,
     }
     print(json.dumps(line), flush=True)
 

@@ -170,6 +170,16 @@ sj_status sj_layout_from_string(const char *name, int32_t *out);
  * recompiles), SJ_ERR_LOAD, SJ_ERR_NOT_INITIALIZED. */
 sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out);
 
+/* Like sj_specialize, but on a miss the handle is built from `code` instead of
+ * being compiled: `code`/`size` must be the code object that sj_handle_code
+ * returned for a SJ_FLAG_COMPILE_ONLY specialization of the same spec, made by
+ * this library version in another process (the caller owns that buffer; it is
+ * copied).  hiprtc serializes compiles within one process, so a tuner spreads
+ * compiles over worker processes and adopts the results here.  A hit returns
+ * the cached handle and ignores `code`.  SJ_ERR_LOAD when the code object does
+ * not load or lacks the expected kernel. */
+sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *code, size_t size, sj_handle *out);
+
 /* Launch a specialization.  No cache lookup happens here.  Pointers by kernel:
  *   SJ_LTIMES:     {L [NM*D] f64, psi [D*G*Z] (f64, or f32 for BF16 dtypes), phi [NM*G*Z] (same type as psi)}
  *   SJ_LPLUSTIMES: {L+ [D*NM] f64, phi [NM*G*Z] f64, psi_out [D*G*Z] f64}

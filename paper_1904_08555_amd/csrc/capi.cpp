@@ -11,6 +11,7 @@
 // launches from the handle without touching the cache.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
@@ -77,7 +78,7 @@ sj_status ensure_device(int *device, const char **arch)
     return SJ_OK;
 }
 
-static sj_status build_handle(const SpecKey &key, sj_handle_ **out)
+static sj_status build_handle(const SpecKey &key, const std::vector<char> *precompiled, sj_handle_ **out)
 {
     auto h = std::make_unique<sj_handle_>();
     h->key = key;
@@ -86,23 +87,29 @@ static sj_status build_handle(const SpecKey &key, sj_handle_ **out)
     h->info.struct_size = sizeof(sj_kernel_info);
     auto t0 = std::chrono::steady_clock::now();
     std::string src;
-    sj_status s = emit_source(key, &src, &h->kernel_name);
+    sj_status s = emit_source(key, &src, &h->kernel_name, &h->kernel_name2);
     if (s != SJ_OK) return s;
     h->info.emit_ms = ms_since(t0);
 
-    t0 = std::chrono::steady_clock::now();
     std::string log;
-    s = rtc_compile(src, key.arch, h->kernel_name, &h->code, &log);
-    h->info.compile_ms = ms_since(t0);
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_stats.compiles++;
-        g_stats.compile_ms_total += h->info.compile_ms;
-        g_stats.emit_ms_total += h->info.emit_ms;
-        if (s != SJ_OK) g_stats.compile_failures++;
+    if (precompiled) {
+        h->code = *precompiled;     // compiled by another process; resource usage unknown here
+        h->info.vgprs = h->info.agprs = h->info.sgprs = -1;
+        h->info.lds_bytes = h->info.scratch_bytes = h->info.occupancy = -1;
+    } else {
+        t0 = std::chrono::steady_clock::now();
+        s = rtc_compile(src, key.arch, h->kernel_name, &h->code, &log);
+        h->info.compile_ms = ms_since(t0);
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_stats.compiles++;
+            g_stats.compile_ms_total += h->info.compile_ms;
+            g_stats.emit_ms_total += h->info.emit_ms;
+            if (s != SJ_OK) g_stats.compile_failures++;
+        }
+        if (s != SJ_OK) return s;
+        parse_resource_usage(log, &h->info);
     }
-    if (s != SJ_OK) return s;
-    parse_resource_usage(log, &h->info);
     h->geom = key_geometry(key);
     h->info.block = (int32_t)h->geom.block;
     h->info.grid = h->geom.grid;
@@ -123,6 +130,8 @@ static sj_status build_handle(const SpecKey &key, sj_handle_ **out)
         hipError_t e = hipModuleLoadData(&h->module, h->code.data());
         if (e != hipSuccess) return fail(SJ_ERR_LOAD, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
         e = hipModuleGetFunction(&h->fn, h->module, h->kernel_name.c_str());
+        if (e == hipSuccess && !h->kernel_name2.empty())
+            e = hipModuleGetFunction(&h->fn2, h->module, h->kernel_name2.c_str());
         if (e != hipSuccess) {
             (void)hipModuleUnload(h->module);
             return fail(SJ_ERR_LOAD, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
@@ -137,7 +146,7 @@ static sj_status build_handle(const SpecKey &key, sj_handle_ **out)
     return SJ_OK;
 }
 
-sj_status get_or_build(const SpecKey &key, sj_handle_ **out)
+sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<char> *precompiled = nullptr)
 {
     std::unique_lock<std::mutex> lk(g_mu);
     g_stats.lookups++;
@@ -164,7 +173,7 @@ sj_status get_or_build(const SpecKey &key, sj_handle_ **out)
     lk.unlock();
 
     sj_handle_ *h = nullptr;
-    sj_status s = build_handle(key, &h);
+    sj_status s = build_handle(key, precompiled, &h);
     std::string msg = (s == SJ_OK) ? std::string() : std::string(sj_last_error());
 
     lk.lock();
@@ -290,6 +299,27 @@ sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out)
     return SJ_OK;
 }
 
+sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *code, size_t size, sj_handle *out)
+{
+    clear_error();
+    if (!spec || !out || !code || size < 4) return fail(SJ_ERR_INVALID_ARG, "null spec, code or output handle");
+    if (std::memcmp(code, "\x7f" "ELF", 4) != 0) return fail(SJ_ERR_LOAD, "code is not an ELF code object");
+    if (spec->flags & SJ_FLAG_COMPILE_ONLY) return fail(SJ_ERR_INVALID_ARG, "adopting code needs a runnable spec");
+    int device = -1;
+    const char *arch = "gfx950";
+    sj_status s = ensure_device(&device, &arch);
+    if (s != SJ_OK) return s;
+    SpecKey key;
+    s = make_key(k, spec, device, arch, &key);
+    if (s != SJ_OK) return s;
+    std::vector<char> bytes((const char *)code, (const char *)code + size);
+    sj_handle_ *h = nullptr;
+    s = get_or_build(key, &h, &bytes);
+    if (s != SJ_OK) return s;
+    *out = h;
+    return SJ_OK;
+}
+
 sj_status sj_emit_source(sj_kernel k, const sj_spec *spec, char *buf, size_t len, size_t *needed)
 {
     clear_error();
@@ -325,6 +355,35 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
         if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
         return SJ_OK;
     }
+    if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD) {
+        const size_t R = (size_t)k.rows, F = (size_t)k.inputs, H = (size_t)k.width;
+        const size_t P = (size_t)mlp_nparams(k.inputs, k.width);
+        hipStream_t st = (hipStream_t)stream;
+        if (k.kernel == SJ_MLP_FWD) {
+            const size_t bytes[3] = {P * 4, R * F * 4, R * 4};
+            sj_status s = check_ptrs(ptrs, nptrs, 3, bytes, 2);
+            if (s != SJ_OK) return s;
+            void *a0 = ptrs[0], *a1 = ptrs[1], *a2 = ptrs[2];
+            void *args[] = {&a0, &a1, &a2};
+            hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0, st, args, nullptr);
+            if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+            return SJ_OK;
+        }
+        const size_t bytes[6] = {P * 4, R * F * 4, R * 4, P * 4, 4, R * (4 * H + 2) * 4};
+        sj_status s = check_ptrs(ptrs, nptrs, 6, bytes, 3);
+        if (s != SJ_OK) return s;
+        void *th = ptrs[0], *X = ptrs[1], *t = ptrs[2], *g = ptrs[3], *loss = ptrs[4], *ws = ptrs[5];
+        void *args1[] = {&th, &X, &t, &ws};
+        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0, st, args1, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        void *args2[] = {&X, &ws, &g, &loss};
+        const unsigned grid2 = (unsigned)((P + 1 + 255) / 256);
+        e = hipModuleLaunchKernel(h->fn2, grid2, 1, 1, 256, 1, 1, 0, st, args2, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
+    if (k.kernel == SJ_ADAM) return fail(SJ_ERR_INVALID_ARG, "Adam handles run through sj_run_adam");
+    if (k.kernel == SJ_BGEMM) return fail(SJ_ERR_INVALID_ARG, "BGEMM handles run through sj_batch_plan / sj_batch_run");
     return fail(SJ_ERR_INVALID_ARG, "this handle is not launched through sj_run");
 }
 
@@ -366,6 +425,32 @@ sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return out;
+}
+
+sj_status sj_run_adam(sj_handle h, void *const *ptrs, int nptrs, int64_t step, double lr, double b1, double b2,
+                      double eps, void *stream)
+{
+    clear_error();
+    if (!h) return fail(SJ_ERR_INVALID_ARG, "null handle");
+    if (!h->runnable) return fail(SJ_ERR_INVALID_ARG, "handle was compiled with SJ_FLAG_COMPILE_ONLY and cannot run");
+    if (h->key.kernel != SJ_ADAM) return fail(SJ_ERR_INVALID_ARG, "handle is not an SJ_ADAM specialization");
+    if (step < 1) return fail(SJ_ERR_INVALID_ARG, "step must be >= 1");
+    if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(SJ_ERR_INVALID_ARG, "need lr > 0, 0 <= b1, b2 < 1, eps > 0");
+    const size_t n = (size_t)h->key.rows;
+    const size_t bytes[4] = {n * 4, n * 4, n * 4, n * 4};
+    // p, m, v are updated in place: each is an output; g is the only pure input.
+    if (!ptrs || nptrs != 4) return fail(SJ_ERR_INVALID_ARG, "Adam takes {p, g, m, v}");
+    sj_status s = check_ptrs(ptrs, nptrs, 4, bytes, 0);
+    if (s != SJ_OK) return s;
+    float flr = (float)lr, fb1 = (float)b1, fb2 = (float)b2, feps = (float)eps;
+    float c1 = (float)(1.0 - std::pow(b1, (double)step)), c2 = (float)(1.0 - std::pow(b2, (double)step));
+    void *p = ptrs[0], *g = ptrs[1], *m = ptrs[2], *v = ptrs[3];
+    void *args[] = {&p, &g, &m, &v, &flr, &fb1, &fb2, &feps, &c1, &c2};
+    hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0, (hipStream_t)stream, args,
+                                         nullptr);
+    if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+    return SJ_OK;
 }
 
 sj_status sj_handle_info(sj_handle h, sj_kernel_info *out)

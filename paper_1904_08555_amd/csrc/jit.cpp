@@ -208,12 +208,56 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         (void)outn;
         return (*out = key), SJ_OK;
     }
+    if (k == SJ_MLP_FWD || k == SJ_MLP_BWD || k == SJ_ADAM) {
+        if (s->dtype != SJ_F32) return fail(SJ_ERR_INVALID_ARG, "the MLP kernels are FP32 (dtype SJ_F32)");
+        if (s->rows < 1 || s->rows > (int64_t(1) << 24)) return fail(SJ_ERR_INVALID_ARG, "rows must be in [1, 2^24]");
+        key.rows = s->rows;
+        if (k != SJ_ADAM) {
+            if (s->inputs < 1 || s->inputs > 64) return fail(SJ_ERR_INVALID_ARG, "inputs must be in [1, 64]");
+            if (s->width < 1 || s->width > 128) return fail(SJ_ERR_INVALID_ARG, "width must be in [1, 128]");
+            if (mlp_nparams(s->inputs, s->width) * 4 > 64 * 1024)
+                return fail(SJ_ERR_UNSUPPORTED, "MLP parameters exceed 64 KiB of LDS");
+            key.inputs = s->inputs;
+            key.width = s->width;
+        }
+        key.block = s->block ? s->block : (k == SJ_ADAM ? 256 : 64);
+        if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+        key.order = 1;
+        return (*out = key), SJ_OK;
+    }
+    if (k == SJ_BGEMM) {
+        if (s->dtype != SJ_F64) return fail(SJ_ERR_INVALID_ARG, "BGEMM is FP64 (dtype SJ_F64)");
+        uint32_t mask = s->class_mask ? s->class_mask : 0x1FFFEu;   // bits 1..16
+        if (mask & ~0x1FFFEu) return fail(SJ_ERR_INVALID_ARG, "class_mask may only set bits 1..16");
+        key.class_mask = mask;
+        key.block = s->block ? s->block : 256;
+        if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+        int r = s->unroll ? s->unroll : 1;
+        if (r != 1 && r != 2 && r != 4) return fail(SJ_ERR_INVALID_ARG, "BGEMM unroll (output rows per thread) must be 1, 2 or 4");
+        key.unroll = r;
+        if (s->tile_n != 0 || s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_n / tile_k");
+        int64_t lds = 0;
+        for (int n = 1; n <= 16; ++n)
+            if (mask & (1u << n)) {
+                const int64_t rn = r * n <= 16 ? r : std::max(1, 16 / n);
+                const int64_t tpi = (n + rn - 1) / rn, slots = key.block / tpi;
+                const int64_t pitch = (n * n) % 2 == 0 ? n * n + 1 : n * n;
+                lds = std::max(lds, slots * pitch);
+            }
+        if (lds * 8 > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "BGEMM staging exceeds 160 KiB of LDS; use a smaller block");
+        key.tile_k = (int32_t)lds;   // LDS doubles per workgroup
+        key.variant = SJ_VAR_AUTO;
+        key.order = 1;
+        return (*out = key), SJ_OK;
+    }
     return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
 }
 
 Geometry key_geometry(const SpecKey &k)
 {
     Geometry g{0, (unsigned)k.block};
+    if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
+        g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
         if (k.variant == SJ_VAR_DIRECT) {
             const int64_t nv = k.B * (k.I / k.tile_n);
@@ -244,8 +288,9 @@ static const char *kCommonPrologue =
     "#define SJ_STORE(v, p) (*(p) = (v))\n"
     "#endif\n";
 
-sj_status emit_source(const SpecKey &k, std::string *src, std::string *name)
+sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std::string *name2)
 {
+    if (name2) name2->clear();
     std::ostringstream o;
     const char *body = nullptr;
     o << "// kernel " << k.kernel << " dtype " << k.dtype << " layout " << k.layout << " variant " << k.variant << "\n";
@@ -279,6 +324,31 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name)
             o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n#define SJ_KERNEL_NAME " << *name << "\n";
             body = kTpl_ltimes_bf16;
         }
+    }
+    if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {
+        o << "#define SJ_R " << k.rows << "\n#define SJ_F " << (k.inputs ? k.inputs : 1) << "\n#define SJ_H "
+          << (k.width ? k.width : 1) << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT 0\n"
+          << "#define SJ_WANT_FWD " << (k.kernel == SJ_MLP_FWD) << "\n#define SJ_WANT_BWD " << (k.kernel == SJ_MLP_BWD)
+          << "\n#define SJ_WANT_ADAM " << (k.kernel == SJ_ADAM) << "\n";
+        body = kTpl_mlp;
+        if (k.kernel == SJ_MLP_FWD) {
+            *name = "sj_mlp_fwd";
+        } else if (k.kernel == SJ_MLP_BWD) {
+            *name = "sj_mlp_bwd_rows";
+            if (name2) *name2 = "sj_mlp_bwd_params";
+        } else {
+            *name = "sj_adam";
+        }
+    }
+    if (k.kernel == SJ_BGEMM) {
+        o << "#define SJ_BLOCK " << k.block << "\n#define SJ_R " << k.unroll << "\n#define SJ_LDS_DOUBLES " << k.tile_k
+          << "\n#define SJ_CLASS_CASES";
+        for (int n = 1; n <= 16; ++n)
+            if (k.class_mask & (1u << n))
+                o << " case " << n << ": sj_bgemm_item<" << n << ">(start, count, order, off, A, B, C, lds); break;";
+        o << "\n#define SJ_NT 0\n";
+        body = kTpl_bgemm;
+        *name = "sj_bgemm_persistent";
     }
     if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");
     o << kCommonPrologue;

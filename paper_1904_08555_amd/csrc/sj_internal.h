@@ -47,7 +47,11 @@ void clear_error();
 sj_status make_key(sj_kernel k, const sj_spec *spec, int device, const char *arch, SpecKey *out);
 
 // Source text (prologue + embedded template) and the kernel's symbol name.
-sj_status emit_source(const SpecKey &key, std::string *src, std::string *kernel_name);
+sj_status emit_source(const SpecKey &key, std::string *src, std::string *kernel_name,
+                      std::string *kernel_name2 = nullptr);
+
+// Number of parameters of the cost-model MLP with `inputs` features and width `width`.
+inline int64_t mlp_nparams(int64_t inputs, int64_t width) { return width * inputs + width * width + 3 * width + 1; }
 
 // Launch geometry of a resolved key.
 struct Geometry {
@@ -77,8 +81,10 @@ struct sj_handle_ {
     uint64_t hash = 0;
     std::string kernel_name;
     std::vector<char> code;
+    std::string kernel_name2;     // second kernel of the module (MLP backward), empty if none
     hipModule_t module = nullptr;
     hipFunction_t fn = nullptr;
+    hipFunction_t fn2 = nullptr;
     sj::Geometry geom{0, 0};
     sj_kernel_info info{};
     bool runnable = false;

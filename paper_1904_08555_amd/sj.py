@@ -53,7 +53,7 @@ SJ_FLAG_INDEX64 = 0x2
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 
 EXPORTED = (
-    "sj_init", "sj_layout_from_string", "sj_specialize", "sj_run", "sj_generic_run", "sj_batch_plan",
+    "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",
     "sj_batch_run", "sj_batch_graph_capture", "sj_batch_graph_launch", "sj_batch_plan_arrays", "sj_plan_destroy",
     "sj_run_adam", "sj_time_run", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
     "sj_last_error", "sj_status_string",
@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
         "sj_init": [ctypes.c_int],
         "sj_layout_from_string": [ctypes.c_char_p, P(i32)],
         "sj_specialize": [ctypes.c_int, P(sj_spec), P(vp)],
+        "sj_specialize_with_code": [ctypes.c_int, P(sj_spec), ctypes.c_char_p, ctypes.c_size_t, P(vp)],
         "sj_run": [vp, P(vp), ctypes.c_int, vp],
         "sj_generic_run": [ctypes.c_int, P(sj_spec), P(vp), ctypes.c_int, vp],
         "sj_batch_plan": [vp, vp, i64, P(vp)],
@@ -243,6 +244,14 @@ def sj_specialize(kernel: int, spec: sj_spec | None = None, **kw) -> Handle:
         spec = make_spec(**kw)
     out = ctypes.c_void_p()
     _check(lib().sj_specialize(int(kernel), ctypes.byref(spec), ctypes.byref(out)))
+    return Handle(out.value, int(kernel))
+
+
+def sj_specialize_with_code(kernel: int, code: bytes, spec: sj_spec | None = None, **kw) -> Handle:
+    if spec is None:
+        spec = make_spec(**kw)
+    out = ctypes.c_void_p()
+    _check(lib().sj_specialize_with_code(int(kernel), ctypes.byref(spec), code, len(code), ctypes.byref(out)))
     return Handle(out.value, int(kernel))
 
 

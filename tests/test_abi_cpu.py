@@ -170,3 +170,50 @@ def test_product_path_has_no_oracle_dependency():
                 with open(os.path.join(dirpath, fn)) as f:
                     text = f.read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, fn)
+
+
+def test_bgemm_and_mlp_specs_compile(P):
+    h = P.sj_specialize(P.SJ_BGEMM, flags=P.SJ_FLAG_COMPILE_ONLY)
+    info = P.sj_handle_info(h)
+    assert info["kernel_name"] == "sj_bgemm_persistent" and info["scratch_bytes"] == 0
+    src = P.sj_emit_source(P.SJ_BGEMM, class_mask=(1 << 3) | (1 << 9))
+    assert "sj_bgemm_item<3>" in src and "sj_bgemm_item<9>" in src and "sj_bgemm_item<4>" not in src
+    for k in (P.SJ_MLP_FWD, P.SJ_MLP_BWD):
+        h = P.sj_specialize(k, dtype=P.SJ_F32, rows=64, inputs=24, width=64, flags=P.SJ_FLAG_COMPILE_ONLY)
+        assert P.sj_handle_info(h)["scratch_bytes"] == 0
+    h = P.sj_specialize(P.SJ_ADAM, dtype=P.SJ_F32, rows=1000, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_adam"
+
+
+@pytest.mark.parametrize("kernel,bad", [
+    ("SJ_BGEMM", dict(class_mask=1)), ("SJ_BGEMM", dict(unroll=3)), ("SJ_BGEMM", dict(dtype=1)),
+    ("SJ_BGEMM", dict(tile_n=4)),
+    ("SJ_MLP_FWD", dict(dtype=3, rows=0, inputs=4, width=4)), ("SJ_MLP_FWD", dict(dtype=3, rows=4, inputs=65, width=4)),
+    ("SJ_MLP_BWD", dict(dtype=0, rows=4, inputs=4, width=4)), ("SJ_ADAM", dict(dtype=3, rows=0)),
+])
+def test_bgemm_mlp_invalid_specs(P, kernel, bad):
+    spec = dict(flags=P.SJ_FLAG_COMPILE_ONLY)
+    spec.update(bad)
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(getattr(P, kernel), **spec)
+    assert e.value.status in (P.SJ_ERR_INVALID_ARG, P.SJ_ERR_UNSUPPORTED)
+
+
+def test_compile_farm_matches_local_compile(P):
+    """Worker processes produce the same code object the parent compiles."""
+    from paper_1904_08555_amd import farm
+    spec = dict(layout="GDZ", Z=123, G=7, D=24, NM=9)
+    with farm.CompileFarm(2) as f:
+        res = f.compile([(P.SJ_LTIMES, spec), (P.SJ_LTIMES, dict(spec, Z=0))])
+    code, ms, err = res[0]
+    assert err is None and code[:4] == b"\x7fELF" and ms > 0
+    assert res[1][0] is None and res[1][2][0] == P.SJ_ERR_INVALID_ARG
+    local = P.sj_handle_code(P.sj_specialize(P.SJ_LTIMES, flags=P.SJ_FLAG_COMPILE_ONLY, **spec))
+    # comgr embeds per-compile temporary names, so bytes differ; size and symbol agree
+    assert len(local) == len(code) and b"sj_ltimes_direct" in code and b"sj_ltimes_direct" in local
+
+
+def test_specialize_with_code_rejects_garbage(P):
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize_with_code(P.SJ_LTIMES, b"not a code object", layout="DGZ", Z=1, G=1, D=1, NM=1)
+    assert e.value.status in (P.SJ_ERR_LOAD, P.SJ_ERR_NOT_INITIALIZED)
