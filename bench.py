@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU baseline sample")
     ap.add_argument("--tile", default="", help="override tile params, e.g. 'tile_n=2,unroll=8,block=256'")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker"),
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -76,6 +76,8 @@ def main():
         return bench_bf16(a)
     if a.workload == "picker":
         return bench_picker(a)
+    if a.workload == "copy":
+        return bench_copy(a)
     return bench_moments(a)
 
 
@@ -401,6 +403,23 @@ def bench_bf16(a):
                      "frac": best["frac"], "traffic": None, "kernel": "sj_ltimes_bf16x3", "bytes_per_launch": b32},
         "modes": res,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_copy(a):
+    """Plain device-to-device copy of 1 GiB (known traffic: 1 GiB read and
+    1 GiB written per dispatch).  Used to calibrate the FETCH_SIZE and
+    WRITE_SIZE counters against which the kernels' HBM traffic is scaled."""
+    import torch
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    med, mean = time_launches(lambda: dst.copy_(src), max(3, a.steps), stream)
+    line = {"metric": "device copy GB/s (read + write)", "value": round(2 * n * 8 / (med * 1e-3) / 1e9, 1),
+            "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": 0, "ms_per_step": round(med, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "ones",
+            "config": {"workload": "copy 1 GiB float64", "read_bytes": n * 8, "write_bytes": n * 8}}
     print(json.dumps(line), flush=True)
 
 

@@ -4,6 +4,7 @@
 // specialization once, sorts the batch into size classes once, and a captured
 // graph replays the single launch).
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -16,12 +17,14 @@ struct sj_plan_ {
     sj_handle_ *h = nullptr;
     int device = -1;
     int64_t count = 0, total = 0;
-    int nwork = 0;
+    int nwin = 0;
     unsigned grid = 0;
-    int32_t *n_dev = nullptr;
-    int64_t *off_dev = nullptr;
-    int32_t *order_dev = nullptr;
-    int32_t *work_dev = nullptr;
+    int32_t *n_dev = nullptr;      // caller's order (generic kernel)
+    int64_t *off_dev = nullptr;    // caller's order (generic kernel)
+    int32_t *win_dev = nullptr;    // per window: first element (lo, hi), element count
+    int32_t *witem_dev = nullptr;  // per window: first work item; one extra entry
+    int32_t *item_dev = nullptr;   // per item: n, first loff index, count, 0
+    int32_t *loff_dev = nullptr;   // per instance: element offset inside its window
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -37,8 +40,10 @@ void free_plan(sj_plan_ *p)
     if (p->cap) (void)hipStreamDestroy(p->cap);
     (void)hipFree(p->n_dev);
     (void)hipFree(p->off_dev);
-    (void)hipFree(p->order_dev);
-    (void)hipFree(p->work_dev);
+    (void)hipFree(p->win_dev);
+    (void)hipFree(p->witem_dev);
+    (void)hipFree(p->item_dev);
+    (void)hipFree(p->loff_dev);
     delete p;
 }
 
@@ -57,12 +62,10 @@ sj_status check_abc(const sj_plan_ *p, const double *A, const double *B, const d
 
 sj_status launch(sj_plan_ *p, const double *A, const double *B, double *C, hipStream_t st)
 {
-    if (p->nwork == 0) return SJ_OK;
-    const int32_t *work = p->work_dev;
-    int nwork = p->nwork;
-    const int32_t *order = p->order_dev;
-    const int64_t *off = p->off_dev;
-    void *args[] = {&work, &nwork, &order, &off, &A, &B, &C};
+    if (p->nwin == 0) return SJ_OK;
+    const int32_t *win = p->win_dev, *witem = p->witem_dev, *item = p->item_dev, *loff = p->loff_dev;
+    int nwin = p->nwin;
+    void *args[] = {&win, &witem, &nwin, &item, &loff, &A, &B, &C};
     hipError_t e = hipModuleLaunchKernel(p->h->fn, p->grid, 1, 1, p->h->geom.block, 1, 1, 0, st, args, nullptr);
     if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
     return SJ_OK;
@@ -80,10 +83,8 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     if (!h->runnable) return fail(SJ_ERR_INVALID_ARG, "handle was compiled with SJ_FLAG_COMPILE_ONLY");
     if (count < 0 || count > 2147483647LL) return fail(SJ_ERR_INVALID_ARG, "count must be in [0, 2^31-1]");
     const uint32_t mask = h->key.class_mask;
-    const int R = h->key.unroll, block = h->key.block;
-    // Counting sort by size class; offsets in the caller's order.
+    // Offsets in the caller's order.
     std::vector<int64_t> off((size_t)count);
-    std::vector<int64_t> per_class(17, 0);
     int64_t total = 0;
     for (int64_t i = 0; i < count; ++i) {
         const int32_t n = n_host[i];
@@ -91,33 +92,44 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
         if (!(mask & (1u << n))) return fail(SJ_ERR_INVALID_ARG, "instance size " + std::to_string(n) + " not in the handle's class mask");
         off[(size_t)i] = total;
         total += (int64_t)n * n;
-        per_class[n]++;
     }
-    std::vector<int64_t> first(17, 0);
-    for (int n = 2; n <= 16; ++n) first[n] = first[n - 1] + per_class[n - 1];
-    std::vector<int32_t> order((size_t)count);
-    {
-        std::vector<int64_t> pos = first;
-        for (int64_t i = 0; i < count; ++i) order[(size_t)pos[n_host[i]]++] = (int32_t)i;
+    // Windows: runs of consecutive whole instances with at most `wmax` elements
+    // per array.  Inside a window, instances are grouped by size class (stable)
+    // into work items of up to `u` instances.  Windows stay in memory order, so
+    // each array is read and written as one contiguous stream.
+    const int64_t wmax = h->key.tile_n, u = h->key.unroll;
+    std::vector<int32_t> win, witem, item, loff;
+    loff.reserve((size_t)count);
+    std::vector<int64_t> bucket[17];
+    int64_t i0 = 0;
+    while (i0 < count) {
+        int64_t i1 = i0, len = 0;
+        while (i1 < count && len + (int64_t)n_host[i1] * n_host[i1] <= wmax) len += (int64_t)n_host[i1] * n_host[i1], ++i1;
+        const int64_t base = off[(size_t)i0];
+        win.push_back((int32_t)(uint32_t)(base & 0xffffffffu));
+        win.push_back((int32_t)(base >> 32));
+        win.push_back((int32_t)len);
+        witem.push_back((int32_t)(item.size() / 4));
+        for (int n = 1; n <= 16; ++n) bucket[n].clear();
+        for (int64_t i = i0; i < i1; ++i) bucket[n_host[i]].push_back(i);
+        for (int n = 1; n <= 16; ++n)
+            for (size_t s0 = 0; s0 < bucket[n].size(); s0 += (size_t)u) {
+                const size_t s1 = std::min(bucket[n].size(), s0 + (size_t)u);
+                item.push_back(n);
+                item.push_back((int32_t)loff.size());
+                item.push_back((int32_t)(s1 - s0));
+                item.push_back(0);
+                for (size_t t = s0; t < s1; ++t) loff.push_back((int32_t)(off[(size_t)bucket[n][t]] - base));
+            }
+        i0 = i1;
     }
-    std::vector<int32_t> work;
-    for (int n = 1; n <= 16; ++n) {
-        if (!per_class[n]) continue;
-        const int64_t rn = R * n <= 16 ? R : std::max(1, 16 / n);   // rows per thread, as in the kernel
-        const int64_t slots = block / ((n + rn - 1) / rn);
-        for (int64_t s = 0; s < per_class[n]; s += slots) {
-            work.push_back(n);
-            work.push_back((int32_t)(first[n] + s));
-            work.push_back((int32_t)std::min<int64_t>(slots, per_class[n] - s));
-            work.push_back(0);
-        }
-    }
+    witem.push_back((int32_t)(item.size() / 4));
     auto p = new sj_plan_();
     p->h = h;
     p->count = count;
     p->total = total;
-    p->nwork = (int)(work.size() / 4);
-    p->grid = (unsigned)std::min<int64_t>(p->nwork, 2048);
+    p->nwin = (int)(win.size() / 3);
+    p->grid = (unsigned)std::min<int64_t>(p->nwin, 2048);
     if (hipGetDevice(&p->device) != hipSuccess) {
         free_plan(p);
         return fail(SJ_ERR_HIP, "hipGetDevice failed");
@@ -130,8 +142,10 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     std::vector<int32_t> n_copy(n_host, n_host + count);
     if (!up((void **)&p->n_dev, n_copy.data(), (size_t)count * 4) ||
         !up((void **)&p->off_dev, off.data(), (size_t)count * 8) ||
-        !up((void **)&p->order_dev, order.data(), (size_t)count * 4) ||
-        !up((void **)&p->work_dev, work.data(), work.size() * 4)) {
+        !up((void **)&p->win_dev, win.data(), win.size() * 4) ||
+        !up((void **)&p->witem_dev, witem.data(), witem.size() * 4) ||
+        !up((void **)&p->item_dev, item.data(), item.size() * 4) ||
+        !up((void **)&p->loff_dev, loff.data(), loff.size() * 4)) {
         free_plan(p);
         return fail(SJ_ERR_OOM, "device allocation or upload of the plan failed");
     }

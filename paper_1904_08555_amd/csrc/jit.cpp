@@ -232,21 +232,16 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         key.class_mask = mask;
         key.block = s->block ? s->block : 256;
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
-        int r = s->unroll ? s->unroll : 1;
-        if (r != 1 && r != 2 && r != 4) return fail(SJ_ERR_INVALID_ARG, "BGEMM unroll (output rows per thread) must be 1, 2 or 4");
-        key.unroll = r;
-        if (s->tile_n != 0 || s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_n / tile_k");
-        int64_t lds = 0;
-        for (int n = 1; n <= 16; ++n)
-            if (mask & (1u << n)) {
-                const int64_t rn = r * n <= 16 ? r : std::max(1, 16 / n);
-                const int64_t tpi = (n + rn - 1) / rn, slots = key.block / tpi;
-                const int64_t pitch = (n * n) % 2 == 0 ? n * n + 1 : n * n;
-                lds = std::max(lds, slots * pitch);
-            }
-        if (lds * 8 > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "BGEMM staging exceeds 160 KiB of LDS; use a smaller block");
-        key.tile_k = (int32_t)lds;   // LDS doubles per workgroup
-        key.variant = SJ_VAR_AUTO;
+        const int u = s->unroll ? s->unroll : 4;
+        if (u != 1 && u != 2 && u != 4 && u != 8)
+            return fail(SJ_ERR_INVALID_ARG, "BGEMM unroll (instances per work item) must be 1, 2, 4 or 8");
+        key.unroll = u;
+        const int win = s->tile_n ? s->tile_n : 4096;
+        if (win < 256 || win > 10240)
+            return fail(SJ_ERR_INVALID_ARG, "BGEMM tile_n (window elements per array, LDS) must be in [256, 10240]");
+        key.tile_n = win;
+        if (s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_k");
+        key.variant = SJ_VAR_MFMA;
         key.order = 1;
         return (*out = key), SJ_OK;
     }
@@ -288,6 +283,9 @@ static const char *kCommonPrologue =
     "#define SJ_STORE(v, p) (*(p) = (v))\n"
     "#endif\n";
 
+// The templates name their kernel through this macro.
+static const char *base_name_macro(const SpecKey &) { return "SJ_KERNEL_NAME"; }
+
 sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std::string *name2)
 {
     if (name2) name2->clear();
@@ -301,7 +299,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
         o << "#define SJ_BLOCK " << k.block << "\n";
         // streaming hint: skip cache retention when every fetched line is used at once
-        const int nt = (k.variant == SJ_VAR_STAGED) ? 1 : (k.I * (k.tile_n ? k.tile_n : 1) >= 16 ? 1 : 0);
+        const int nt = (k.variant != SJ_VAR_DIRECT) ? 1 : (k.I * (k.tile_n ? k.tile_n : 1) >= 16 ? 1 : 0);
         o << "#define SJ_NT " << nt << "\n";
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
@@ -317,11 +315,10 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT "
               << (lt ? k.NM : k.D) << "\n#define SJ_RT " << k.tile_n << "\n#define SJ_WREG " << k.unroll << "\n";
             *name = lt ? "sj_ltimes_rows_mfma" : "sj_lplustimes_rows_mfma";
-            o << "#define SJ_KERNEL_NAME " << *name << "\n";
             body = kTpl_rows_mfma64;
         } else if (k.variant == SJ_VAR_MFMA) {
             *name = (k.dtype == SJ_BF16X3) ? "sj_ltimes_bf16x3" : "sj_ltimes_bf16";
-            o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n#define SJ_KERNEL_NAME " << *name << "\n";
+            o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n";
             body = kTpl_ltimes_bf16;
         }
     }
@@ -341,16 +338,22 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         }
     }
     if (k.kernel == SJ_BGEMM) {
-        o << "#define SJ_BLOCK " << k.block << "\n#define SJ_R " << k.unroll << "\n#define SJ_LDS_DOUBLES " << k.tile_k
+        o << "#define SJ_BLOCK " << k.block << "\n#define SJ_U " << k.unroll << "\n#define SJ_WMAX " << k.tile_n
           << "\n#define SJ_CLASS_CASES";
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
-                o << " case " << n << ": sj_bgemm_item<" << n << ">(start, count, order, off, A, B, C, lds); break;";
+                o << " case " << n << ": it = sj_bgemm_class<" << n << ">(item, loff, it, i1, As, Bs); break;";
         o << "\n#define SJ_NT 0\n";
         body = kTpl_bgemm;
         *name = "sj_bgemm_persistent";
     }
     if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+        // one symbol per nesting, so profiles tell the layouts apart
+        static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
+        *name += std::string("_") + lay[k.layout];
+        o << "#define " << base_name_macro(k) << " " << *name << "\n";
+    }
     o << kCommonPrologue;
     if (k.flags & SJ_FLAG_DEBUG_FAIL_COMPILE)
         o << "static_assert(SJ_BLOCK < 0, \"compile failure requested by SJ_FLAG_DEBUG_FAIL_COMPILE\");\n";

@@ -94,7 +94,7 @@ def test_compile_only_cache_and_canonical_keys(P):
     assert s1["compiles"] - s0["compiles"] == 1
     assert s1["hits"] - s0["hits"] == 1
     info = P.sj_handle_info(h1)
-    assert info["kernel_name"] == "sj_ltimes_direct"
+    assert info["kernel_name"] == "sj_ltimes_direct_dzg"
     assert info["compile_ms"] > 0 and info["code_bytes"] > 1000
     assert info["vgprs"] > 0 and info["sgprs"] > 0 and info["scratch_bytes"] == 0
     code = P.sj_handle_code(h1)
@@ -187,7 +187,7 @@ def test_bgemm_and_mlp_specs_compile(P):
 
 @pytest.mark.parametrize("kernel,bad", [
     ("SJ_BGEMM", dict(class_mask=1)), ("SJ_BGEMM", dict(unroll=3)), ("SJ_BGEMM", dict(dtype=1)),
-    ("SJ_BGEMM", dict(tile_n=4)),
+    ("SJ_BGEMM", dict(tile_n=-1)), ("SJ_BGEMM", dict(tile_k=2)),
     ("SJ_MLP_FWD", dict(dtype=3, rows=0, inputs=4, width=4)), ("SJ_MLP_FWD", dict(dtype=3, rows=4, inputs=65, width=4)),
     ("SJ_MLP_BWD", dict(dtype=0, rows=4, inputs=4, width=4)), ("SJ_ADAM", dict(dtype=3, rows=0)),
 ])

@@ -1,4 +1,4 @@
-"""GPU parity of the batched small products (persistent per-class kernel, its
+"""GPU parity of the batched small products (per-class MFMA kernel over a work list, its
 HIP-graph replay, and the generic per-instance kernel) against the FP64
 oracle.  Bar: |C - C_oracle| <= 1e-12 * (|A||B|)_ij per entry; bit-exact for
 identity and small-integer inputs."""
@@ -58,8 +58,8 @@ def run_plan(P, n, A_d, B_d, C_d, graph=False, **spec):
         P.sj_plan_destroy(plan)
 
 
-@pytest.mark.parametrize("spec", [dict(), dict(unroll=2), dict(unroll=4, block=128), dict(block=512),
-                                  dict(block=64)], ids=["default", "r2", "r4b128", "b512", "b64"])
+@pytest.mark.parametrize("spec", [dict(), dict(tile_n=256), dict(unroll=1, block=128), dict(unroll=8, block=512),
+                                  dict(unroll=2, block=64, tile_n=1000)], ids=["default", "w256", "u1b128", "u8b512", "u2b64"])
 @pytest.mark.parametrize("lohi", [(3, 16), (1, 16), (1, 4), (16, 16)], ids=["n3-16", "n1-16", "n1-4", "n16"])
 def test_bgemm_small_batches(P, orc, spec, lohi):
     n, off, A, B = batch(7, 777, *lohi)

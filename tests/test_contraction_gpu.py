@@ -257,7 +257,7 @@ def test_same_key_same_handle_and_stats(P):
     s1 = P.sj_stats()
     assert s1["compiles"] - s0["compiles"] <= 1 and s1["hits"] - s0["hits"] >= 1
     info = P.sj_handle_info(h1)
-    assert info["kernel_name"] == "sj_ltimes_direct" and info["load_ms"] > 0 and info["scratch_bytes"] == 0
+    assert info["kernel_name"] == "sj_ltimes_direct_zdg" and info["load_ms"] > 0 and info["scratch_bytes"] == 0
 
 
 MFMA_SHAPES = [(150, 3, 37, 9), (64, 4, 96, 16), (33, 1, 5, 3), (16, 1, 16, 16), (40, 2, 17, 20), (7, 3, 128, 64)]
