@@ -177,7 +177,7 @@ def test_bgemm_and_mlp_specs_compile(P):
     info = P.sj_handle_info(h)
     assert info["kernel_name"] == "sj_bgemm_persistent" and info["scratch_bytes"] == 0
     src = P.sj_emit_source(P.SJ_BGEMM, class_mask=(1 << 3) | (1 << 9))
-    assert "sj_bgemm_item<3>" in src and "sj_bgemm_item<9>" in src and "sj_bgemm_item<4>" not in src
+    assert "sj_bgemm_class<3>" in src and "sj_bgemm_class<9>" in src and "sj_bgemm_class<4>" not in src
     for k in (P.SJ_MLP_FWD, P.SJ_MLP_BWD):
         h = P.sj_specialize(k, dtype=P.SJ_F32, rows=64, inputs=24, width=64, flags=P.SJ_FLAG_COMPILE_ONLY)
         assert P.sj_handle_info(h)["scratch_bytes"] == 0
