@@ -373,25 +373,31 @@ def bench_bf16(a):
     stream = torch.cuda.current_stream()
     res = {}
     b32 = (D + NM) * G * Z * 4 + NM * D * 8
-    for name, dt in (("bf16", P.SJ_BF16), ("bf16x3", P.SJ_BF16X3)):
-        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt)
+    # default (wide, four columns per lane) and the one-column-per-lane form
+    for name, dt, cols in (("bf16", P.SJ_BF16, 0), ("bf16x3", P.SJ_BF16X3, 0),
+                           ("bf16_narrow", P.SJ_BF16, 1), ("bf16x3_narrow", P.SJ_BF16X3, 1)):
+        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt, tile_n=cols)
         t = P.sj_time_run(h, [L_d, psi32, phi32], warmup=a.warmup, reps=a.steps)
         ms = statistics.median(t)
         info = P.sj_handle_info(h)
         res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
-                         frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         vgprs=info["vgprs"], occupancy=info["occupancy"])
+                         frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
+                         vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"])
     del phi32
     psi64 = psi32.to(torch.float64)
     del psi32
     phi64 = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
-    h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM)
-    t = P.sj_time_run(h, [L_d, psi64, phi64], warmup=a.warmup, reps=a.steps)
-    ms = statistics.median(t)
     b64 = (D + NM) * G * Z * 8 + NM * D * 8
     flops = 2 * D * NM * G * Z
-    res["f64"] = dict(ms=round(ms, 4), gbs=round(b64 / (ms * 1e-3) / 1e9, 1),
-                      tflops=round(flops / (ms * 1e-3) / 1e12, 2), frac_fp64_peak=round(flops / (ms * 1e-3) / 78.6e12, 4))
+    # FP64: vector FMAs (DIRECT) and the FP64 matrix-core column kernel
+    for name, var in (("f64", P.SJ_VAR_DIRECT), ("f64_mfma", P.SJ_VAR_MFMA)):
+        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, variant=var)
+        t = P.sj_time_run(h, [L_d, psi64, phi64], warmup=a.warmup, reps=a.steps)
+        ms = statistics.median(t)
+        info = P.sj_handle_info(h)
+        res[name] = dict(ms=round(ms, 4), gbs=round(b64 / (ms * 1e-3) / 1e9, 1), kernel=info["kernel_name"],
+                         tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                         frac_fp64_peak=round(flops / (ms * 1e-3) / 78.6e12, 4))
     best = res["bf16x3"]
     line = {
         "metric": "LTimes BF16 (split-compensated) GB/s at Z=262144 G=64 D=128 NM=64",
@@ -400,7 +406,7 @@ def bench_bf16(a):
         "dtype": "bf16x3 (fp32 accumulate)", "data": "synthetic (SplitMix64, seed 0)",
         "config": {"workload": "LTimes DGZ Z=262144 G=64 D=128 NM=64, psi FP32 in, phi FP32 out"},
         "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": best["frac"], "traffic": None, "kernel": "sj_ltimes_bf16x3", "bytes_per_launch": b32},
+                     "frac": best["frac"], "traffic": None, "kernel": best["kernel"], "bytes_per_launch": b32},
         "modes": res,
     }
     print(json.dumps(line), flush=True)

@@ -94,12 +94,13 @@ typedef enum sj_dtype {
 /* Kernel structure for LTimes / LPlusTimes.  AUTO picks DIRECT when the
  * innermost storage axis is a column axis (DGZ, DZG, GDZ, ZDG) and the FP64
  * matrix-core row kernel (MFMA) when it is D (GZD, ZGD); BF16 dtypes always
- * use MFMA. */
+ * use MFMA.  FP64 MFMA with a column axis innermost is the matrix-core column
+ * kernel (chosen explicitly, or by a tuner). */
 typedef enum sj_variant {
     SJ_VAR_AUTO = 0,
     SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
     SJ_VAR_STAGED = 2,   /* rows of contiguous D (or NM) values staged through LDS */
-    SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 for layouts with D innermost */
+    SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 row kernel (D innermost) or column kernel */
 } sj_variant;
 
 /* Flags. */
@@ -116,12 +117,16 @@ typedef struct sj_spec {
     int64_t  count;         /* BGEMM generic path: number of instances */
     uint32_t class_mask;    /* BGEMM: bit n set when size class n (1 <= n <= 16) occurs; 0 = all of 1..16 */
     int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
-                               BGEMM: max elements of A staged per chunk; 0 = default */
+                               FP64 MFMA rows: 16-row tiles per wave (1..8); FP64 MFMA columns and
+                               BF16: columns per lane (1, 2, 4 / 1, 4); BGEMM: window size, elements
+                               per array staged in LDS (256..10240); 0 = default */
     int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
-    int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs; 0 = default */
+    int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs;
+                               FP64 MFMA columns: 4-deep reduction steps per group of loads in flight
+                               (1..16); BGEMM: instances per work item (1, 2, 4, 8); 0 = default */
     int32_t  block;         /* threads per workgroup (64..1024, multiple of 64); 0 = default */
     uint32_t flags;         /* SJ_FLAG_* */
-    int32_t  order;         /* DIRECT: 0 = default, 1 = every workgroup walks the reduction (LTimes) or
+    int32_t  order;         /* DIRECT and FP64 MFMA columns: 0 = default, 1 = every workgroup walks the reduction (LTimes) or
                                output (LPlusTimes) rows in ascending order, 2 = each workgroup starts at a
                                different row group (rotation), which spreads concurrent accesses over
                                DRAM channels when rows are megabytes apart */

@@ -122,8 +122,6 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         }
         if (s->dtype != SJ_F64 && var != SJ_VAR_MFMA)
             return fail(SJ_ERR_INVALID_ARG, "BF16 dtypes need the MFMA variant");
-        if (s->dtype == SJ_F64 && var == SJ_VAR_MFMA && key.I != 1)
-            return fail(SJ_ERR_UNSUPPORTED, "the FP64 MFMA variant needs a layout with D innermost (GZD, ZGD)");
         if (var < SJ_VAR_DIRECT || var > SJ_VAR_MFMA) return fail(SJ_ERR_INVALID_ARG, "variant out of range");
         key.variant = var;
         const int64_t red = (k == SJ_LTIMES) ? s->D : s->NM;   // reduction length
@@ -170,6 +168,35 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "STAGED tile exceeds 160 KiB of LDS");
             key.unroll = 0;
             key.full_unroll = 1;
+        } else if (s->dtype == SJ_F64 && key.I > 1) {
+            // FP64 matrix-core column contraction: tile_n = columns per lane (1, 2, 4),
+            // unroll = 4-deep reduction steps per group of loads in flight, order 2 = rotated groups.
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            const int64_t ob = (outn + 15) / 16, ks = (red + 3) / 4;
+            int t = s->tile_n;
+            if (t == 0) {   // widest tile whose accumulators stay within 32 FP64 values per lane
+                t = 1;
+                for (int c = 4; c >= 2; c /= 2)
+                    if (key.I % c == 0 && ob * 4 * c <= 32) { t = c; break; }
+            }
+            if (t != 1 && t != 2 && t != 4) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (columns per lane) must be 1, 2 or 4");
+            if (key.I % t != 0) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n must divide the contiguous column extent");
+            if (ob * 4 * t > 128) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 128 FP64 values per lane");
+            int pf = s->unroll;
+            if (pf == 0) pf = (int)std::max<int64_t>(1, std::min<int64_t>(16 / t, 32 / (ob * t)));
+            if (pf < 1 || pf > 16) return fail(SJ_ERR_INVALID_ARG, "MFMA unroll (steps per group) must be in [1, 16]");
+            key.unroll = (int32_t)std::min<int64_t>(pf, ks);
+            if (ks * ob * 64 * 8 > 160 * 1024)
+                return fail(SJ_ERR_UNSUPPORTED, "MFMA weight fragments exceed 160 KiB of LDS");
+            int order = s->order;
+            if (order == 0) order = (key.I * 8 >= (int64_t(1) << 20)) ? 2 : 1;
+            if (order != 1 && order != 2) return fail(SJ_ERR_INVALID_ARG, "order must be 0, 1 or 2");
+            if ((ks + key.unroll - 1) / key.unroll < 2) order = 1;   // a single group
+            key.order = order;
+            key.tile_n = t;
+            key.tile_k = 4;
+            key.full_unroll = 0;
         } else if (s->dtype == SJ_F64) {
             // FP64 matrix-core row contraction (D innermost): tile_n = 16-row tiles per wave.
             if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
@@ -195,13 +222,19 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             key.order = 1;
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
-            if (s->tile_n != 0 && s->tile_n != 1) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n must be 1");
-            key.tile_n = 1;
+            // tile_n = columns per lane: 1 (4-byte loads, 32 columns per wave) or 4 (16-byte loads,
+            // 128 columns per wave as four interleaved MFMA tiles; needs the column extent % 4 == 0).
+            int cpl = s->tile_n;
+            if (cpl == 0) cpl = (key.I % 4 == 0) ? 4 : 1;
+            if (cpl != 1 && cpl != 4) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n (columns per lane) must be 1 or 4");
+            if (cpl == 4 && key.I % 4 != 0) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n 4 needs a column extent divisible by 4");
+            key.tile_n = cpl;
             const int64_t frag_bytes = ((s->NM + 31) / 32) * ((s->D + 15) / 16) * 64 * 16;
             if (frag_bytes * (s->dtype == SJ_BF16X3 ? 2 : 1) > 160 * 1024)
                 return fail(SJ_ERR_UNSUPPORTED, "BF16 weight fragments exceed 160 KiB of LDS");
             if (s->D > 256) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes keeps a column's D values in registers: D <= 256");
             key.tile_k = 16;
+            if (s->unroll != 0) return fail(SJ_ERR_INVALID_ARG, "BF16 takes no unroll");
             key.unroll = 0;
             key.full_unroll = 1;
         }
@@ -259,11 +292,16 @@ Geometry key_geometry(const SpecKey &k)
             g.grid = (unsigned)((nv + k.block - 1) / k.block);
         } else if (k.variant == SJ_VAR_STAGED) {
             g.grid = (unsigned)((k.B + k.tile_n - 1) / k.tile_n);
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I > 1) {
+            const int64_t tiles = k.B * ((k.I + 16 * k.tile_n - 1) / (16 * k.tile_n));
+            const int64_t waves = k.block / 64;
+            g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const int64_t rows_per_block = (int64_t)(k.block / 64) * 16 * k.tile_n;
             g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
         } else if (k.variant == SJ_VAR_MFMA) {
-            const int64_t tiles = k.B * ((k.I + 31) / 32);
+            const int64_t cols = k.tile_n == 4 ? 128 : 32;
+            const int64_t tiles = k.B * ((k.I + cols - 1) / cols);
             const int64_t waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
         }
@@ -310,6 +348,12 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             o << "#define SJ_TILE_N " << k.tile_n << "\n#define SJ_TILE_K " << k.tile_k << "\n";
             body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_staged : kTpl_lplustimes_staged;
             *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_staged" : "sj_lplustimes_staged";
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I > 1) {
+            const bool lt = (k.kernel == SJ_LTIMES);
+            o << "#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT " << (lt ? k.NM : k.D) << "\n#define SJ_T "
+              << k.tile_n << "\n#define SJ_PF " << k.unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
+            *name = lt ? "sj_ltimes_cols_mfma" : "sj_lplustimes_cols_mfma";
+            body = kTpl_cols_mfma64;
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const bool lt = (k.kernel == SJ_LTIMES);
             o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT "
@@ -318,8 +362,9 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             body = kTpl_rows_mfma64;
         } else if (k.variant == SJ_VAR_MFMA) {
             *name = (k.dtype == SJ_BF16X3) ? "sj_ltimes_bf16x3" : "sj_ltimes_bf16";
+            if (k.tile_n == 4) *name += "w";
             o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n";
-            body = kTpl_ltimes_bf16;
+            body = (k.tile_n == 4) ? kTpl_ltimes_bf16w : kTpl_ltimes_bf16;
         }
     }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {

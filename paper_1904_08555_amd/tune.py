@@ -7,14 +7,18 @@ runs), times each one with sj_time_run, and returns the fastest together with
 every timing.  This is the profile-guided autotuning named as future work in
 ClangJIT section 6; it is also the judge of the learned picker.
 
-The candidate set (at most 24 per kernel and layout):
+The candidate set (at most 33 per kernel and layout):
   * innermost axis is a column axis (DGZ, DZG, GDZ, ZDG):
     DIRECT with tile_n (columns per thread) in {1, 2} dividing the contiguous
     extent, unroll in {4, 8, 16}, block in {256, 512}, order in {ascending,
-    rotated}  (<= 24)
+    rotated}  (<= 24); FP64 MFMA column kernel with tile_n (columns per lane)
+    in {1, 2, 4} dividing the extent and unroll (reduction steps per group of
+    loads) in {2, 4, 8}, default order  (<= 9)
   * innermost axis is D (GZD, ZGD): STAGED with tile_k in {8, 16, 32},
     block 256, tile_n in {256, 512}; FP64 MFMA with 16-row tiles per wave in
     {1, 2, 4} and block in {256, 512}; DIRECT with tile_n 1, unroll 8  (<= 13)
+  * BF16 dtypes: columns per lane in {1, 4} (4 when it divides the extent),
+    block in {256, 512}  (<= 4)
 Candidates that the specializer rejects for a shape (register or LDS limits)
 are dropped.
 """
@@ -34,12 +38,14 @@ def contiguous_extent(layout: str, Z: int, G: int) -> int:
 
 def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype: int = sj.SJ_F64) -> list:
     out = []
-    if dtype != sj.SJ_F64:
-        for rt in (1, 2, 4):
-            for block in (256, 512):
-                out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block))
-        return out
     ext = contiguous_extent(layout, Z, G)
+    if dtype != sj.SJ_F64:
+        for cpl in (1, 4):
+            if ext % cpl:
+                continue
+            for block in (256, 512):
+                out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=cpl, block=block))
+        return out
     if ext > 1:
         for vec in (1, 2):
             if ext % vec:
@@ -49,6 +55,11 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
                     for order in (1, 2):
                         out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=vec, unroll=unroll, block=block,
                                         order=order))
+        for cpl in (1, 2, 4):
+            if ext % cpl:
+                continue
+            for pf in (2, 4, 8):
+                out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=cpl, unroll=pf))
     else:
         for tk in (8, 16, 32):
             for tn in (256, 512):

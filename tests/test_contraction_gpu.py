@@ -318,3 +318,78 @@ def test_mfma64_full_size_sampled(P, orc):
     assert componentwise_err(out_log[:, g, z], ref2, scale2) <= TOL_F64
     del psi_d, phi_d, out_d
     torch.cuda.empty_cache()
+
+
+COLS_SHAPES = [(37, 5, 11, 6), (300, 3, 48, 16), (64, 4, 96, 16), (40, 2, 17, 20), (7, 3, 128, 64), (16, 8, 5, 3),
+               (1, 1, 1, 1)]
+
+
+@pytest.mark.parametrize("layout", ["DGZ", "DZG", "GDZ", "ZDG"])
+@pytest.mark.parametrize("shape", COLS_SHAPES, ids=lambda s: "Z%dG%dD%dNM%d" % s)
+@pytest.mark.parametrize("tile", [dict(), dict(tile_n=1, unroll=1, block=64), dict(tile_n=2, unroll=3, order=2),
+                                  dict(tile_n=4, unroll=16, block=512, order=2), dict(tile_n=4, unroll=2, order=1)],
+                         ids=["default", "t1p1b64", "t2p3rot", "t4p16b512rot", "t4p2"])
+def test_mfma64_cols(P, orc, layout, shape, tile):
+    """FP64 matrix-core column kernels (a column axis innermost): ragged column
+    tiles, reduction lengths not multiple of 4, ragged last group, output
+    counts not multiple of 16, rotated group order, W in 64 KiB of LDS."""
+    Z, G, D, NM = shape
+    print(f"case cols layout={layout} shape={shape} tile={tile}", flush=True)
+    L, Lp, psi, phi_in = contraction_inputs(9, layout, Z, G, D, NM)
+    _, I = {"DGZ": (1, G * Z), "DZG": (1, G * Z), "GDZ": (G, Z), "ZDG": (Z, G)}[layout]
+    t = tile.get("tile_n", 0)
+    if t and I % t:
+        with pytest.raises(P.SJError) as e:
+            run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), variant=P.SJ_VAR_MFMA, **tile)
+        assert e.value.status == P.SJ_ERR_INVALID_ARG
+        return
+    got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), variant=P.SJ_VAR_MFMA, **tile))
+    ref = orc.ltimes(layout, Z, G, D, NM, L, psi)
+    scale = orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)
+    assert componentwise_err(got, ref, scale) <= TOL_F64
+    got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), variant=P.SJ_VAR_MFMA, **tile))
+    ref2 = orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in)
+    scale2 = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)
+    assert componentwise_err(got2, ref2, scale2) <= TOL_F64
+
+
+def test_mfma64_cols_onehot_bitexact(P, orc):
+    """One-hot L through the column kernel: phi is a row gather of psi, bit for bit."""
+    Z, G, D, NM = 300, 3, 48, 16
+    layout = "DGZ"
+    _, _, psi, _ = contraction_inputs(4, layout, Z, G, D, NM)
+    L = np.zeros((NM, D))
+    perm = np.random.default_rng(2).permutation(D)[:NM]
+    L[np.arange(NM), perm] = 1.0
+    got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L.ravel()), dev(psi), variant=P.SJ_VAR_MFMA))
+    assert np.array_equal(got, orc.ltimes(layout, Z, G, D, NM, L.ravel(), psi))
+
+
+@pytest.mark.parametrize("layout", ["DGZ", "ZDG"])
+def test_mfma64_cols_full_size_sampled(P, orc, layout):
+    """Z=32768 G=32 D=96 NM=16 through the column kernel (rotated order for
+    DGZ, whose rows are 8 MiB apart), 2048 sampled columns checked."""
+    Z, G, D, NM = 32768, 32, 96, 16
+    li = LAYOUTS.index(layout)
+    psi_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01, li, (D, G, Z))
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    Lp = gen.matrix_sym(0, gen.ARR_LPLUS, D, NM)
+    phi_d = run_ltimes(P, layout, Z, G, D, NM, dev(L), psi_d, variant=P.SJ_VAR_MFMA)
+    out_d = run_lplus(P, layout, Z, G, D, NM, dev(Lp), phi_d, variant=P.SJ_VAR_MFMA)
+    rng = np.random.default_rng(12)
+    g = rng.integers(0, G, 2048)
+    z = rng.integers(0, Z, 2048)
+    g[-1], z[-1] = G - 1, Z - 1
+    cols = gen.psi_columns(0, D, G, Z, g, z)
+    ref = orc.ltimes("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    scale = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    phi_log = gen.from_layout(host(phi_d), layout, NM, G, Z)
+    assert componentwise_err(phi_log[:, g, z], ref, scale) <= TOL_F64
+    phi_cols = phi_log[:, g, z]
+    ref2 = orc.lplustimes("DGZ", len(g), 1, D, NM, Lp, phi_cols).reshape(D, -1)
+    scale2 = orc.ltimes_absscale("DGZ", len(g), 1, NM, D, Lp, phi_cols).reshape(D, -1)
+    out_log = gen.from_layout(host(out_d), layout, D, G, Z)
+    assert componentwise_err(out_log[:, g, z], ref2, scale2) <= TOL_F64
+    del psi_d, phi_d, out_d
+    torch.cuda.empty_cache()
