@@ -129,11 +129,23 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     p->count = count;
     p->total = total;
     p->nwin = (int)(win.size() / 3);
-    p->grid = (unsigned)std::min<int64_t>(p->nwin, 2048);
     if (hipGetDevice(&p->device) != hipSuccess) {
         free_plan(p);
         return fail(SJ_ERR_HIP, "hipGetDevice failed");
     }
+    // Persistent grid: as many workgroups as the device holds at once (from the
+    // compiler's occupancy and LDS figures), each walking windows grid-stride.
+    int cus = 0;
+    int64_t resident = 2048;
+    const sj_kernel_info &ki = h->info;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0 &&
+        ki.occupancy > 0) {
+        const int64_t waves_per_wg = h->geom.block / 64;
+        int64_t per_cu = std::max<int64_t>(1, (int64_t)ki.occupancy * 4 / waves_per_wg);
+        if (ki.lds_bytes > 0) per_cu = std::min<int64_t>(per_cu, std::max(1, (160 * 1024) / ki.lds_bytes));
+        resident = (int64_t)cus * std::min<int64_t>(per_cu, 16);
+    }
+    p->grid = (unsigned)std::min<int64_t>(p->nwin, resident);
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (!bytes) return true;
         if (hipMalloc(dst, bytes) != hipSuccess) return false;

@@ -275,7 +275,11 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         key.tile_n = win;
         if (s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_k");
         key.variant = SJ_VAR_MFMA;
-        key.order = 1;
+        // order: 1 = the next window is loaded after the current one is written back,
+        // 2 = its loads are issued before the current window's products (prefetch)
+        const int order = s->order ? s->order : 1;
+        if (order != 1 && order != 2) return fail(SJ_ERR_INVALID_ARG, "BGEMM order must be 0, 1 or 2");
+        key.order = order;
         return (*out = key), SJ_OK;
     }
     return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
@@ -388,7 +392,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
                 o << " case " << n << ": it = sj_bgemm_class<" << n << ">(item, loff, it, i1, As, Bs); break;";
-        o << "\n#define SJ_NT 0\n";
+        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT 0\n";
         body = kTpl_bgemm;
         *name = "sj_bgemm_persistent";
     }

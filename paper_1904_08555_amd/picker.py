@@ -12,9 +12,11 @@ section 6.
 Shapes (LTimes): Z = k^3 with k ~ U{8..64}, G ~ U{8..128}, D = 8 U{2..32},
 NM ~ U{4, 9, 16, 36, 64}, dtype ~ U{FP64, BF16x3}.  Candidates:
   FP64, column axis innermost (DGZ, DZG, GDZ, ZDG): DIRECT, tile_n in {1, 2},
-      order in {ascending, rotated}, unroll 8, block 256;
+      order in {ascending, rotated}, unroll 8, block 256; FP64-MFMA columns
+      with default tiles, order in {ascending, rotated};
   FP64, D innermost (GZD, ZGD): FP64-MFMA rows, tile_n in {1, 2, 4};
-  BF16x3 (column layouts only): block in {256, 512}.
+  BF16x3 (column layouts only): columns per lane in {1, 4} (4 when it
+      divides the contiguous extent), block 256.
 The cost of a candidate is the median of 3 timed launches of one LTimes (after
 one warm-up), with L2 and the last-level cache flushed first when the working
 set is under 512 MB.  Regret of a pick: t(pick) / min_c t(c) - 1.
@@ -58,13 +60,17 @@ def candidates(shape: dict) -> list:
                     for order in (1, 2):
                         out.append(dict(layout=lay, variant=sj.SJ_VAR_DIRECT, tile_n=vec, unroll=8, block=256,
                                         order=order))
+                for order in (1, 2):
+                    out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, order=order))
             else:
                 for rt in (1, 2, 4):
                     out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, tile_n=rt, block=256))
     else:
         for lay in COLUMN_LAYOUTS:
-            for block in (256, 512):
-                out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, block=block))
+            ext = contiguous_extent(lay, shape["Z"], shape["G"])
+            for cpl in (1, 4):
+                if ext % cpl == 0:
+                    out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, tile_n=cpl, block=256))
     return out
 
 
