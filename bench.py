@@ -139,6 +139,24 @@ def bench_moments(a):
         lib.sj_specialize(kid, sref, ctypes.byref(hout))
     hit_us = (time.perf_counter() - t0) / n_hit * 1e6
 
+    # The same from 8 host threads at once (ctypes drops the interpreter lock
+    # during the call, so the threads contend on the cache's mutex).
+    import threading
+
+    def hammer(out, idx):
+        h8 = ctypes.c_void_p()
+        r0 = time.perf_counter()
+        for _ in range(n_hit // 4):
+            lib.sj_specialize(kid, sref, ctypes.byref(h8))
+        out[idx] = (time.perf_counter() - r0) / (n_hit // 4) * 1e6
+    per_thread = [0.0] * 8
+    ths = [threading.Thread(target=hammer, args=(per_thread, i)) for i in range(8)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    hit_us_8 = statistics.median(per_thread)
+
     arrs = {}
     for lay in layouts:
         psi, phi, out = bufs[lay]
@@ -261,6 +279,7 @@ def bench_moments(a):
         "generic": generic,
         "jit": jit,
         "cache_hit_us": round(hit_us, 3),
+        "cache_hit_us_8_threads": round(hit_us_8, 3),
     }
     print(json.dumps(line), flush=True)
 

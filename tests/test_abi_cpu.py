@@ -187,7 +187,7 @@ def test_bgemm_and_mlp_specs_compile(P):
 
 @pytest.mark.parametrize("kernel,bad", [
     ("SJ_BGEMM", dict(class_mask=1)), ("SJ_BGEMM", dict(unroll=3)), ("SJ_BGEMM", dict(dtype=1)),
-    ("SJ_BGEMM", dict(tile_n=-1)), ("SJ_BGEMM", dict(tile_k=2)),
+    ("SJ_BGEMM", dict(tile_n=-1)), ("SJ_BGEMM", dict(tile_k=2)), ("SJ_BGEMM", dict(order=3)),
     ("SJ_MLP_FWD", dict(dtype=3, rows=0, inputs=4, width=4)), ("SJ_MLP_FWD", dict(dtype=3, rows=4, inputs=65, width=4)),
     ("SJ_MLP_BWD", dict(dtype=0, rows=4, inputs=4, width=4)), ("SJ_ADAM", dict(dtype=3, rows=0)),
 ])
@@ -217,3 +217,42 @@ def test_specialize_with_code_rejects_garbage(P):
     with pytest.raises(P.SJError) as e:
         P.sj_specialize_with_code(P.SJ_LTIMES, b"not a code object", layout="DGZ", Z=1, G=1, D=1, NM=1)
     assert e.value.status in (P.SJ_ERR_LOAD, P.SJ_ERR_NOT_INITIALIZED)
+
+
+def test_matrix_core_column_and_bf16_specs(P):
+    """FP64 MFMA column kernel and BF16 forms: names, resolved tiles and
+    rejected tiles, compiled without a GPU."""
+    base = dict(Z=4096, G=8, D=48, NM=16, flags=P.SJ_FLAG_COMPILE_ONLY)
+    h = P.sj_specialize(P.SJ_LTIMES, layout="GDZ", variant=P.SJ_VAR_MFMA, **base)
+    info = P.sj_handle_info(h)
+    assert info["kernel_name"] == "sj_ltimes_cols_mfma_gdz" and info["tile_n"] == 4 and info["scratch_bytes"] == 0
+    h = P.sj_specialize(P.SJ_LPLUSTIMES, layout="ZDG", variant=P.SJ_VAR_MFMA, **base)
+    info = P.sj_handle_info(h)
+    # 48 outputs per column = 3 blocks of 16: the accumulator budget allows 2 columns per lane
+    assert info["kernel_name"] == "sj_lplustimes_cols_mfma_zdg" and info["tile_n"] == 2
+    src = P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", variant=P.SJ_VAR_MFMA, order=2, unroll=3, **base)
+    assert "#define SJ_ROTATE 1" in src and "#define SJ_PF 3" in src
+    for bad in (dict(tile_n=3), dict(unroll=17), dict(order=5)):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_LTIMES, layout="DGZ", variant=P.SJ_VAR_MFMA, **dict(base, **bad))
+        assert e.value.status == P.SJ_ERR_INVALID_ARG
+    with pytest.raises(P.SJError) as e:   # 4 columns per lane need the contiguous extent % 4 == 0
+        P.sj_specialize(P.SJ_LTIMES, layout="ZDG", variant=P.SJ_VAR_MFMA, tile_n=4,
+                        **dict(base, G=6))
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", dtype=P.SJ_BF16X3, **base)
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_ltimes_bf16x3w_dgz"
+    h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", dtype=P.SJ_BF16, tile_n=1, **base)
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_ltimes_bf16_dgz"
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_LTIMES, layout="ZDG", dtype=P.SJ_BF16, tile_n=4, **dict(base, G=6))
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+def test_bgemm_prefetch_form(P):
+    src1 = P.sj_emit_source(P.SJ_BGEMM)
+    src2 = P.sj_emit_source(P.SJ_BGEMM, order=2)
+    assert "#define SJ_PREFETCH 0" in src1 and "#define SJ_PREFETCH 1" in src2
+    h1 = P.sj_specialize(P.SJ_BGEMM, flags=P.SJ_FLAG_COMPILE_ONLY)
+    h2 = P.sj_specialize(P.SJ_BGEMM, order=2, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert h1 != h2 and P.sj_handle_info(h2)["scratch_bytes"] == 0
