@@ -107,8 +107,8 @@ def test_bf16_d_innermost_unsupported(P):
 
 def test_bf16_large_config_sampled(P, orc):
     """Z=262144 G=64 D=128 NM=64 (psi has 2^31 elements: 64-bit indexing), DGZ,
-    both modes and the FP64 path on the same values; sampled columns against
-    the oracle.  Reports the observed maximum errors."""
+    both modes in both the wide (default) and narrow forms; sampled columns
+    against the oracle.  Reports the observed maximum errors."""
     Z, G, D, NM = 262144, 64, 128, 64
     psi_d = torch.empty(D * G * Z, dtype=torch.float32, device="cuda")
     gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01_24, 0, (D, G, Z))
@@ -123,15 +123,51 @@ def test_bf16_large_config_sampled(P, orc):
     scale = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
     flat = (g.astype(np.int64) * Z + z)
     errs = {}
-    for dt, bound in ((P.SJ_BF16, 2 * UB + UB * UB + gs(D + 1)), (P.SJ_BF16X3, 3 * UB * UB + gs(3 * D + 1))):
-        phi_d = run_bf16(P, dt, "DGZ", Z, G, D, NM, L_d, psi_d)
-        idx = torch.from_numpy(np.arange(NM)[:, None] * (G * Z) + flat[None, :]).cuda()
-        got = host(phi_d[idx.reshape(-1)]).astype(np.float64).reshape(NM, -1)
-        errs[dt] = componentwise_err(got, exact, scale)
-        assert errs[dt] <= bound
+    idx = torch.from_numpy(np.arange(NM)[:, None] * (G * Z) + flat[None, :]).cuda().reshape(-1)
+    for cols_per_lane in (0, 1):
+        for dt, bound in ((P.SJ_BF16, 2 * UB + UB * UB + gs(D + 1)), (P.SJ_BF16X3, 3 * UB * UB + gs(3 * D + 1))):
+            phi_d = run_bf16(P, dt, "DGZ", Z, G, D, NM, L_d, psi_d, tile_n=cols_per_lane)
+            got = host(phi_d[idx]).astype(np.float64).reshape(NM, -1)
+            errs[(dt, cols_per_lane)] = componentwise_err(got, exact, scale)
+            assert errs[(dt, cols_per_lane)] <= bound
+            del phi_d
+            torch.cuda.empty_cache()
+    print("observed max componentwise error: plain %.3e / %.3e, compensated %.3e / %.3e (wide / narrow)"
+          % (errs[(P.SJ_BF16, 0)], errs[(P.SJ_BF16, 1)], errs[(P.SJ_BF16X3, 0)], errs[(P.SJ_BF16X3, 1)]))
+    for c in (0, 1):
+        assert errs[(P.SJ_BF16X3, c)] < errs[(P.SJ_BF16, c)] / 50
+    del psi_d
+    torch.cuda.empty_cache()
+
+
+def test_fp64_large_config_sampled(P, orc):
+    """The FP64 paths the benchmark times beside BF16 at Z=262144 G=64 D=128
+    NM=64 (DGZ, psi 17 GB): vector FMAs (DIRECT) and the FP64 matrix-core
+    column kernel, on the same 24-bit values; sampled columns against the
+    oracle at the FP64 bar."""
+    from helpers import TOL_F64
+    Z, G, D, NM = 262144, 64, 128, 64
+    psi_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01_24, 0, (D, G, Z))
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    L_d = dev(L)
+    rng = np.random.default_rng(6)
+    g = rng.integers(0, G, 1024)
+    z = rng.integers(0, Z, 1024)
+    g[:2], z[:2] = [0, G - 1], [0, Z - 1]
+    cols = gen.psi_columns(0, D, G, Z, g, z, bits24=True)
+    exact = orc.ltimes("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    scale = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    flat = (g.astype(np.int64) * Z + z)
+    idx = torch.from_numpy(np.arange(NM)[:, None] * (G * Z) + flat[None, :]).cuda().reshape(-1)
+    for var in (P.SJ_VAR_DIRECT, P.SJ_VAR_MFMA):
+        print(f"case fp64 large variant={var}", flush=True)
+        phi_d = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
+        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, variant=var)
+        P.sj_run(h, [L_d, psi_d, phi_d])
+        got = host(phi_d[idx]).reshape(NM, -1)
+        assert componentwise_err(got, exact, scale) <= TOL_F64
         del phi_d
         torch.cuda.empty_cache()
-    print(f"observed max componentwise error: plain {errs[P.SJ_BF16]:.3e}, compensated {errs[P.SJ_BF16X3]:.3e}")
-    assert errs[P.SJ_BF16X3] < errs[P.SJ_BF16] / 50
     del psi_d
     torch.cuda.empty_cache()

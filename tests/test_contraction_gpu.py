@@ -337,6 +337,12 @@ def test_mfma64_cols(P, orc, layout, shape, tile):
     print(f"case cols layout={layout} shape={shape} tile={tile}", flush=True)
     L, Lp, psi, phi_in = contraction_inputs(9, layout, Z, G, D, NM)
     _, I = {"DGZ": (1, G * Z), "DZG": (1, G * Z), "GDZ": (G, Z), "ZDG": (Z, G)}[layout]
+    if I == 1:
+        # a contiguous extent of 1 is a row contraction: the specializer takes the
+        # FP64 MFMA row kernel (its tiles are covered by test_mfma64_rows)
+        h = P.sj_specialize(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, variant=P.SJ_VAR_MFMA)
+        assert "rows_mfma" in P.sj_handle_info(h)["kernel_name"]
+        tile = {}
     t = tile.get("tile_n", 0)
     if t and I % t:
         with pytest.raises(P.SJError) as e:
