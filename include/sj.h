@@ -119,7 +119,7 @@ typedef struct sj_spec {
     int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
                                FP64 MFMA rows: 16-row tiles per wave (1..8); FP64 MFMA columns and
                                BF16: columns per lane (1, 2, 4 / 1, 4); BGEMM: window size, elements
-                               per array staged in LDS (256..10240); 0 = default */
+                               per array staged in LDS (256..7168); 0 = default */
     int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
     int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs;
                                FP64 MFMA columns: 4-deep reduction steps per group of loads in flight

@@ -21,10 +21,8 @@ struct sj_plan_ {
     unsigned grid = 0;
     int32_t *n_dev = nullptr;      // caller's order (generic kernel)
     int64_t *off_dev = nullptr;    // caller's order (generic kernel)
-    int32_t *win_dev = nullptr;    // per window: first element (lo, hi), element count
-    int32_t *witem_dev = nullptr;  // per window: first work item; one extra entry
-    int32_t *item_dev = nullptr;   // per item: n, first loff index, count, 0
-    int32_t *loff_dev = nullptr;   // per instance: element offset inside its window
+    int32_t *win_dev = nullptr;    // 8 ints per window (see the kernel template)
+    int32_t *meta_dev = nullptr;   // per window: packed work items, then 16-bit instance offsets
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -41,9 +39,7 @@ void free_plan(sj_plan_ *p)
     (void)hipFree(p->n_dev);
     (void)hipFree(p->off_dev);
     (void)hipFree(p->win_dev);
-    (void)hipFree(p->witem_dev);
-    (void)hipFree(p->item_dev);
-    (void)hipFree(p->loff_dev);
+    (void)hipFree(p->meta_dev);
     delete p;
 }
 
@@ -63,9 +59,9 @@ sj_status check_abc(const sj_plan_ *p, const double *A, const double *B, const d
 sj_status launch(sj_plan_ *p, const double *A, const double *B, double *C, hipStream_t st)
 {
     if (p->nwin == 0) return SJ_OK;
-    const int32_t *win = p->win_dev, *witem = p->witem_dev, *item = p->item_dev, *loff = p->loff_dev;
+    const int32_t *win = p->win_dev, *meta = p->meta_dev;
     int nwin = p->nwin;
-    void *args[] = {&win, &witem, &nwin, &item, &loff, &A, &B, &C};
+    void *args[] = {&win, &nwin, &meta, &A, &B, &C};
     hipError_t e = hipModuleLaunchKernel(p->h->fn, p->grid, 1, 1, p->h->geom.block, 1, 1, 0, st, args, nullptr);
     if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
     return SJ_OK;
@@ -96,56 +92,72 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     // Windows: runs of consecutive whole instances with at most `wmax` elements
     // per array.  Inside a window, instances are grouped by size class (stable)
     // into work items of up to `u` instances.  Windows stay in memory order, so
-    // each array is read and written as one contiguous stream.
+    // each array is read and written as one contiguous stream.  Per window:
+    //   win[8w .. 8w+7] = {first element lo, hi, element count, first meta word,
+    //                      item count, meta word count, 0, 0}
+    //   meta words      = items (n | (count-1) << 5 | first offset index << 8),
+    //                     then the instances' element offsets inside the window
+    //                     as 16-bit values, two per word (first in the low half).
     const int64_t wmax = h->key.tile_n, u = h->key.unroll;
-    std::vector<int32_t> win, witem, item, loff;
-    loff.reserve((size_t)count);
+    std::vector<int32_t> win, meta;
     std::vector<int64_t> bucket[17];
+    std::vector<int32_t> items;
+    std::vector<uint16_t> lo;
     int64_t i0 = 0;
     while (i0 < count) {
         int64_t i1 = i0, len = 0;
         while (i1 < count && len + (int64_t)n_host[i1] * n_host[i1] <= wmax) len += (int64_t)n_host[i1] * n_host[i1], ++i1;
         const int64_t base = off[(size_t)i0];
-        win.push_back((int32_t)(uint32_t)(base & 0xffffffffu));
-        win.push_back((int32_t)(base >> 32));
-        win.push_back((int32_t)len);
-        witem.push_back((int32_t)(item.size() / 4));
         for (int n = 1; n <= 16; ++n) bucket[n].clear();
         for (int64_t i = i0; i < i1; ++i) bucket[n_host[i]].push_back(i);
+        items.clear();
+        lo.clear();
         for (int n = 1; n <= 16; ++n)
             for (size_t s0 = 0; s0 < bucket[n].size(); s0 += (size_t)u) {
                 const size_t s1 = std::min(bucket[n].size(), s0 + (size_t)u);
-                item.push_back(n);
-                item.push_back((int32_t)loff.size());
-                item.push_back((int32_t)(s1 - s0));
-                item.push_back(0);
-                for (size_t t = s0; t < s1; ++t) loff.push_back((int32_t)(off[(size_t)bucket[n][t]] - base));
+                items.push_back(n | (int32_t)((s1 - s0 - 1) << 5) | (int32_t)(lo.size() << 8));
+                for (size_t t = s0; t < s1; ++t) lo.push_back((uint16_t)(off[(size_t)bucket[n][t]] - base));
             }
+        const int64_t m0 = (int64_t)meta.size();
+        meta.insert(meta.end(), items.begin(), items.end());
+        for (size_t t = 0; t < lo.size(); t += 2)
+            meta.push_back((int32_t)((uint32_t)lo[t] | ((uint32_t)(t + 1 < lo.size() ? lo[t + 1] : 0) << 16)));
+        const int64_t mlen = (int64_t)meta.size() - m0;
+        if (m0 > INT32_MAX - mlen) return fail(SJ_ERR_UNSUPPORTED, "batch plan metadata exceeds 2^31 words");
+        win.push_back((int32_t)(uint32_t)(base & 0xffffffffu));
+        win.push_back((int32_t)(base >> 32));
+        win.push_back((int32_t)len);
+        win.push_back((int32_t)m0);
+        win.push_back((int32_t)items.size());
+        win.push_back((int32_t)mlen);
+        win.push_back(0);
+        win.push_back(0);
         i0 = i1;
     }
-    witem.push_back((int32_t)(item.size() / 4));
     auto p = new sj_plan_();
     p->h = h;
     p->count = count;
     p->total = total;
-    p->nwin = (int)(win.size() / 3);
+    p->nwin = (int)(win.size() / 8);
     if (hipGetDevice(&p->device) != hipSuccess) {
         free_plan(p);
         return fail(SJ_ERR_HIP, "hipGetDevice failed");
     }
-    // Persistent grid: as many workgroups as the device holds at once (from the
-    // compiler's occupancy and LDS figures), each walking windows grid-stride.
+    // Wave form: one wave per window.  Workgroup form: a persistent grid of as
+    // many workgroups as the device holds at once (from the compiler's
+    // occupancy and LDS figures), each walking windows grid-stride.
+    const int64_t waves_per_wg = h->geom.block / 64;
     int cus = 0;
     int64_t resident = 2048;
     const sj_kernel_info &ki = h->info;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0 &&
         ki.occupancy > 0) {
-        const int64_t waves_per_wg = h->geom.block / 64;
         int64_t per_cu = std::max<int64_t>(1, (int64_t)ki.occupancy * 4 / waves_per_wg);
         if (ki.lds_bytes > 0) per_cu = std::min<int64_t>(per_cu, std::max(1, (160 * 1024) / ki.lds_bytes));
         resident = (int64_t)cus * std::min<int64_t>(per_cu, 16);
     }
-    p->grid = (unsigned)std::min<int64_t>(p->nwin, resident);
+    p->grid = (h->key.variant == SJ_VAR_DIRECT) ? (unsigned)((p->nwin + waves_per_wg - 1) / waves_per_wg)
+                                                : (unsigned)std::min<int64_t>(p->nwin, resident);
     auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
         if (!bytes) return true;
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
@@ -155,9 +167,7 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     if (!up((void **)&p->n_dev, n_copy.data(), (size_t)count * 4) ||
         !up((void **)&p->off_dev, off.data(), (size_t)count * 8) ||
         !up((void **)&p->win_dev, win.data(), win.size() * 4) ||
-        !up((void **)&p->witem_dev, witem.data(), witem.size() * 4) ||
-        !up((void **)&p->item_dev, item.data(), item.size() * 4) ||
-        !up((void **)&p->loff_dev, loff.data(), loff.size() * 4)) {
+        !up((void **)&p->meta_dev, meta.data(), meta.size() * 4)) {
         free_plan(p);
         return fail(SJ_ERR_OOM, "device allocation or upload of the plan failed");
     }

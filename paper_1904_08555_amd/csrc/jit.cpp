@@ -263,22 +263,35 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
         uint32_t mask = s->class_mask ? s->class_mask : 0x1FFFEu;   // bits 1..16
         if (mask & ~0x1FFFEu) return fail(SJ_ERR_INVALID_ARG, "class_mask may only set bits 1..16");
         key.class_mask = mask;
-        key.block = s->block ? s->block : 256;
+        // variant: MFMA (or AUTO) = workgroup form, the waves of a workgroup share a window and the
+        // grid is persistent; DIRECT = wave form, each wave owns a window copied global -> LDS directly.
+        int var = s->variant ? s->variant : SJ_VAR_MFMA;
+        if (var != SJ_VAR_MFMA && var != SJ_VAR_DIRECT)
+            return fail(SJ_ERR_INVALID_ARG, "BGEMM variant must be SJ_VAR_MFMA (workgroup form) or SJ_VAR_DIRECT (wave form)");
+        key.variant = var;
+        const bool wave_form = (var == SJ_VAR_DIRECT);
+        key.block = s->block ? s->block : (wave_form ? 128 : 256);
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
-        const int u = s->unroll ? s->unroll : 4;
+        const int u = s->unroll ? s->unroll : 2;
         if (u != 1 && u != 2 && u != 4 && u != 8)
             return fail(SJ_ERR_INVALID_ARG, "BGEMM unroll (instances per work item) must be 1, 2, 4 or 8");
         key.unroll = u;
-        const int win = s->tile_n ? s->tile_n : 4096;
-        if (win < 256 || win > 10240)
-            return fail(SJ_ERR_INVALID_ARG, "BGEMM tile_n (window elements per array, LDS) must be in [256, 10240]");
+        const int win = s->tile_n ? s->tile_n : (wave_form ? 512 : 2048);
+        if (win < 256 || win > 7168)
+            return fail(SJ_ERR_INVALID_ARG, "BGEMM tile_n (window elements per array, LDS) must be in [256, 7168]");
         key.tile_n = win;
+        // LDS per workgroup: A and B windows (16 bytes per element) + metadata (at most 6 bytes per
+        // element); the wave form holds one window per wave.
+        const int64_t mmax = win + (win + 1) / 2;
+        const int64_t lds = wave_form ? (int64_t)(key.block / 64) * (2 * ((win + 31) / 32) * 32 * 8 + ((mmax + 63) / 64) * 64 * 4)
+                                      : (int64_t)win * 16 + mmax * 4;
+        if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "BGEMM window and block exceed 160 KiB of LDS");
         if (s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_k");
-        key.variant = SJ_VAR_MFMA;
-        // order: 1 = the next window is loaded after the current one is written back,
-        // 2 = its loads are issued before the current window's products (prefetch)
-        const int order = s->order ? s->order : 1;
+        // order (workgroup form): 1 = the next window is loaded after the current one is written
+        // back, 2 = its loads are issued before the current window's products (prefetch)
+        const int order = s->order ? s->order : (wave_form ? 1 : 2);
         if (order != 1 && order != 2) return fail(SJ_ERR_INVALID_ARG, "BGEMM order must be 0, 1 or 2");
+        if (wave_form && order != 1) return fail(SJ_ERR_INVALID_ARG, "the BGEMM wave form has no prefetch order");
         key.order = order;
         return (*out = key), SJ_OK;
     }
@@ -333,6 +346,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
     if (name2) name2->clear();
     std::ostringstream o;
     const char *body = nullptr;
+    const char *bgemm_common = nullptr;   // shared class bodies of the two batched-product forms
     o << "// kernel " << k.kernel << " dtype " << k.dtype << " layout " << k.layout << " variant " << k.variant << "\n";
     o << "typedef " << (k.index64 ? "long long" : "int") << " sj_index_t;\n";
     const char *sfx = k.index64 ? "LL" : "";
@@ -387,14 +401,16 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         }
     }
     if (k.kernel == SJ_BGEMM) {
+        const bool wave_form = (k.variant == SJ_VAR_DIRECT);
         o << "#define SJ_BLOCK " << k.block << "\n#define SJ_U " << k.unroll << "\n#define SJ_WMAX " << k.tile_n
-          << "\n#define SJ_CLASS_CASES";
+          << "\n#define SJ_ITEM_STEP " << (wave_form ? 1 : k.block / 64) << "\n#define SJ_CLASS_CASES";
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
-                o << " case " << n << ": it = sj_bgemm_class<" << n << ">(item, loff, it, i1, As, Bs); break;";
+                o << " case " << n << ": it = sj_bgemm_class<" << n << ">(Ms, Ls, it, nitems, As, Bs); break;";
         o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT 0\n";
-        body = kTpl_bgemm;
-        *name = "sj_bgemm_persistent";
+        bgemm_common = kTpl_bgemm_common;
+        body = wave_form ? kTpl_bgemm_wave : kTpl_bgemm;
+        *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";
     }
     if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
@@ -406,6 +422,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
     o << kCommonPrologue;
     if (k.flags & SJ_FLAG_DEBUG_FAIL_COMPILE)
         o << "static_assert(SJ_BLOCK < 0, \"compile failure requested by SJ_FLAG_DEBUG_FAIL_COMPILE\");\n";
+    if (bgemm_common) o << bgemm_common;
     o << body;
     *src = o.str();
     return SJ_OK;

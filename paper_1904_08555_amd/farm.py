@@ -50,15 +50,22 @@ class CompileFarm:
     def __exit__(self, *exc):
         self.close()
 
-    def compile(self, items):
-        """items: [(kernel, spec dict)] -> [(code bytes or None, compile_ms, error or None)]."""
-        return self.pool.map(_compile_one, list(items), chunksize=1)
+    def compile(self, items, log=None, every: int = 250):
+        """items: [(kernel, spec dict)] -> [(code bytes or None, compile_ms, error or None)].
+        With `log`, reports progress every `every` finished compiles."""
+        items = list(items)
+        out = []
+        for i, r in enumerate(self.pool.imap(_compile_one, items, chunksize=1)):
+            out.append(r)
+            if log and (i + 1) % every == 0:
+                log(f"compiled {i + 1}/{len(items)}")
+        return out
 
-    def specialize_many(self, items):
+    def specialize_many(self, items, log=None):
         """Compile `items` in the workers and adopt each result in this process.
         Returns [(handle or None, compile_ms, error)] in the order of `items`."""
         out = []
-        for (kernel, spec), (code, ms, err) in zip(items, self.compile(items)):
+        for (kernel, spec), (code, ms, err) in zip(items, self.compile(items, log=log)):
             if code is None:
                 out.append((None, ms, err))
                 continue

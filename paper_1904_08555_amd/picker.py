@@ -150,7 +150,7 @@ def time_items(farm, bufs: Buffers, items, log=None, reps: int = 3):
     """items: [(shape, cand)] -> [median ms or None] (None when the specializer
     rejects the candidate)."""
     t0 = time.time()
-    built = farm.specialize_many([(sj.SJ_LTIMES, spec_of(s, c)) for s, c in items])
+    built = farm.specialize_many([(sj.SJ_LTIMES, spec_of(s, c)) for s, c in items], log=log)
     if log:
         log(f"compiled {len(items)} specializations in {time.time() - t0:.1f}s")
     out = []

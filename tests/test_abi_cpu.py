@@ -250,9 +250,13 @@ def test_matrix_core_column_and_bf16_specs(P):
 
 
 def test_bgemm_prefetch_form(P):
-    src1 = P.sj_emit_source(P.SJ_BGEMM)
-    src2 = P.sj_emit_source(P.SJ_BGEMM, order=2)
+    src1 = P.sj_emit_source(P.SJ_BGEMM, order=1)
+    src2 = P.sj_emit_source(P.SJ_BGEMM)           # prefetching is the default
     assert "#define SJ_PREFETCH 0" in src1 and "#define SJ_PREFETCH 1" in src2
-    h1 = P.sj_specialize(P.SJ_BGEMM, flags=P.SJ_FLAG_COMPILE_ONLY)
+    h1 = P.sj_specialize(P.SJ_BGEMM, order=1, flags=P.SJ_FLAG_COMPILE_ONLY)
     h2 = P.sj_specialize(P.SJ_BGEMM, order=2, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert h2 == P.sj_specialize(P.SJ_BGEMM, flags=P.SJ_FLAG_COMPILE_ONLY)
     assert h1 != h2 and P.sj_handle_info(h2)["scratch_bytes"] == 0
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_BGEMM, tile_n=7169, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG

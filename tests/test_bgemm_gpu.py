@@ -59,7 +59,11 @@ def run_plan(P, n, A_d, B_d, C_d, graph=False, **spec):
 
 
 @pytest.mark.parametrize("spec", [dict(), dict(tile_n=256), dict(unroll=1, block=128), dict(unroll=8, block=512),
-                                  dict(unroll=2, block=64, tile_n=1000)], ids=["default", "w256", "u1b128", "u8b512", "u2b64"])
+                                  dict(unroll=2, block=64, tile_n=1000), dict(order=1),
+                                  dict(variant=1), dict(variant=1, unroll=1, block=64, tile_n=256),
+                                  dict(variant=1, unroll=4, block=256, tile_n=1024), dict(variant=1, unroll=8, block=64)],
+                         ids=["default", "w256", "u1b128", "u8b512", "u2b64", "noprefetch",
+                              "wave", "wave-u1b64w256", "wave-u4b256w1024", "wave-u8b64"])
 @pytest.mark.parametrize("lohi", [(3, 16), (1, 16), (1, 4), (16, 16)], ids=["n3-16", "n1-16", "n1-4", "n16"])
 def test_bgemm_small_batches(P, orc, spec, lohi):
     n, off, A, B = batch(7, 777, *lohi)
@@ -107,7 +111,8 @@ def test_bgemm_empty_plan(P):
     P.sj_plan_destroy(plan)
 
 
-def test_bgemm_graph_replays(P, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["workgroup", "wave"])
+def test_bgemm_graph_replays(P, orc, variant):
     """The captured graph is replayed several times with eager work and
     synchronizations in between; every replay is checked."""
     n, off, A, B = batch(11, 5000)
@@ -115,7 +120,7 @@ def test_bgemm_graph_replays(P, orc):
     scale = abs_scale(n, off, A, B)
     A_d, B_d = dev(A), dev(B)
     C_d = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
-    h = P.sj_specialize(P.SJ_BGEMM)
+    h = P.sj_specialize(P.SJ_BGEMM, variant=variant)
     plan = P.sj_batch_plan(h, n)
     P.sj_batch_graph_capture(plan, A_d, B_d, C_d)
     for rep in range(4):
@@ -143,13 +148,14 @@ def test_bgemm_generic_kernel(P, orc):
     P.sj_plan_destroy(plan)
 
 
-def test_bgemm_config_200k(P, orc):
+@pytest.mark.parametrize("variant", [0, 1], ids=["workgroup", "wave"])
+def test_bgemm_config_200k(P, orc, variant):
     """200,000 instances, n ~ U{3..16}, A and B ~ N(0,1): every entry checked,
     through the graph replay that the benchmark times."""
     n, off, A, B = batch(0, 200000)
     ref = orc.bgemm(n, off[:-1], A, B)
     C_d = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
-    run_plan(P, n, dev(A), dev(B), C_d, graph=True)
+    run_plan(P, n, dev(A), dev(B), C_d, graph=True, variant=variant)
     got = host(C_d)
     # scale for every entry from |A||B| via the oracle on absolute values
     scale = orc.bgemm(n, off[:-1], np.abs(A), np.abs(B))
