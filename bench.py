@@ -6,6 +6,10 @@ time, FP64, Z = 32^3 = 32768 zones, G = 32 groups, D = 96 directions,
 NM = 16 moments; psi ~ U[0,1), L and L+ ~ U[-1,1), seed 0 (counter-based
 generator, values identical across layouts).  One step = for every nesting: the
 specialization lookup (cache hit), LTimes psi -> phi, and LPlusTimes phi -> psi'.
+Before the timed region the exhaustive tuner picks each nesting's and kernel's
+specialization on the resident buffers (compiles in worker processes); the
+same step with the library's default specializations is timed afterwards and
+reported beside it (--no-tune skips the tuning).
 All inputs are resident in HBM before the timed region; each array is 805 MB
 or 134 MB, larger than the 256 MB last-level cache, so every step streams HBM.
 
@@ -50,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU baseline sample")
     ap.add_argument("--tile", default="", help="override tile params, e.g. 'tile_n=2,unroll=8,block=256'")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="moments: time the default specializations only (no exhaustive tuning first)")
     ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
@@ -113,9 +119,30 @@ def bench_moments(a):
     # --- specialization (cold compiles, timed per key) -------------------------------------
     lib = P.lib()
     specs, handles, jit = {}, {}, {}
+    default_specs = {}
     for lay in layouts:
         for kname, kid in (("ltimes", P.SJ_LTIMES), ("lplustimes", P.SJ_LPLUSTIMES)):
-            s = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **tile)
+            default_specs[(lay, kname)] = (kid, P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **tile))
+
+    # --- exhaustive tuning on the resident buffers (compiles in worker processes) ----------
+    tuned, tune_s = {}, None
+    if not a.no_tune and not tile:
+        from paper_1904_08555_amd import tune
+        from paper_1904_08555_amd.farm import CompileFarm
+        t0 = time.perf_counter()
+        with CompileFarm(12) as farm:
+            for lay in layouts:
+                psi, phi, out = bufs[lay]
+                for kname, kid, ptrs in (("ltimes", P.SJ_LTIMES, [L_d, psi, phi]),
+                                         ("lplustimes", P.SJ_LPLUSTIMES, [Lp_d, phi, out])):
+                    r = tune.tune_exhaustive(kid, lay, Z, G, D, NM, ptrs, reps=10, warmup=2, farm=farm)
+                    tuned[(lay, kname)] = r["best"]
+                    print(f"tuned {kname} {lay}: {r['best']} {r['best_ms'] * 1e3:.1f} us "
+                          f"({len(r['results'])} candidates)", file=sys.stderr, flush=True)
+        tune_s = time.perf_counter() - t0
+    for lay in layouts:
+        for kname, kid in (("ltimes", P.SJ_LTIMES), ("lplustimes", P.SJ_LPLUSTIMES)):
+            s = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **(tuned.get((lay, kname)) or tile))
             t0 = time.perf_counter()
             h = P.sj_specialize(kid, s)
             wall = (time.perf_counter() - t0) * 1e3
@@ -165,9 +192,9 @@ def bench_moments(a):
     order = [(lay, k) for lay in layouts for k in ("ltimes", "lplustimes")]
     nbytes = algorithmic_bytes(Z, G, D, NM)
 
-    def step(events=None):
+    def step(events=None, table=specs):
         for key in order:
-            kid, s = specs[key]
+            kid, s = table[key]
             rc = lib.sj_specialize(kid, ctypes.byref(s), ctypes.byref(hout))   # cache lookup (hit)
             if rc != 0:
                 raise RuntimeError(P.sj_last_error())
@@ -203,6 +230,18 @@ def bench_moments(a):
         ms = statistics.median(per_kernel[key])
         kern[f"{key[1]}_{key[0]}"] = dict(us=round(ms * 1e3, 2), gbs=round(nbytes / (ms * 1e-3) / 1e9, 1),
                                            frac=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    # the same step with the default (untuned) specializations
+    default_value = None
+    if tuned:
+        for _ in range(a.warmup):
+            step(table=default_specs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            step(table=default_specs)
+        torch.cuda.synchronize()
+        default_value = step_bytes / ((time.perf_counter() - t0) / a.steps) / 1e9
+
     dom = max(order, key=lambda k: sum(per_kernel[k]))
     dom_ms = statistics.mean(per_kernel[dom])
     achieved = nbytes / (dom_ms * 1e-3) / 1e9
@@ -269,7 +308,9 @@ def bench_moments(a):
         "dtype": "f64",
         "data": "synthetic (SplitMix64 counter generator, seed 0)",
         "config": {"workload": f"LTimes+LPlusTimes, six nestings chosen at run time, FP64, Z={Z} G={G} D={D} NM={NM}",
-                   "layouts": layouts, "step": "per nesting: cache lookup + LTimes + LPlusTimes"},
+                   "layouts": layouts, "step": "per nesting: cache lookup + LTimes + LPlusTimes",
+                   "specialization": ("chosen per nesting and kernel by the exhaustive tuner before the timed region"
+                                      if tuned else "library defaults")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": f"{dom[1]}_{dom[0]}", "avg_us": round(dom_ms * 1e3, 2),
@@ -280,6 +321,9 @@ def bench_moments(a):
         "jit": jit,
         "cache_hit_us": round(hit_us, 3),
         "cache_hit_us_8_threads": round(hit_us_8, 3),
+        "tuned": {f"{k[1]}_{k[0]}": v for k, v in tuned.items()},
+        "tune_s": None if tune_s is None else round(tune_s, 1),
+        "value_default_specializations": None if default_value is None else round(default_value, 1),
     }
     print(json.dumps(line), flush=True)
 
@@ -333,28 +377,36 @@ def bench_batched(a):
     for _ in range(a.warmup):
         P.sj_batch_graph_launch(plan)
     torch.cuda.synchronize()
-    per = []
-    t_total = 0.0
-    for _ in range(a.steps):
-        flush.fill_(1)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        P.sj_batch_graph_launch(plan)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_total += time.perf_counter() - t0
-        per.append(e0.elapsed_time(e1))
+
+    def flushed(fn, reps):
+        """Per-launch event times (ms) and host wall time (s), with the 512 MB
+        scratch write before every launch (the working set fits the LLC otherwise)."""
+        per, wall = [], 0.0
+        for _ in range(reps):
+            flush.fill_(1)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            per.append(e0.elapsed_time(e1))
+        return per, wall
+
+    per, t_total = flushed(lambda: P.sj_batch_graph_launch(plan), a.steps)
     med = statistics.median(per)
     mean = statistics.mean(per)
+    run_per, _ = flushed(lambda: P.sj_batch_run(plan, A_d, B_d, C_d), max(3, a.steps // 2))
     n_dev, off_dev, _ = P.sj_batch_plan_arrays(plan)
     gspec = P.make_spec(count=count)
 
     def generic():
         P.sj_generic_run(P.SJ_BGEMM, [n_dev, off_dev, A_d, B_d, C_d], gspec)
     generic()
-    gmed, _ = time_launches(generic, max(3, a.steps // 2), stream)
+    gper, _ = flushed(generic, max(3, a.steps // 2))
+    gmed = statistics.median(gper)
     info = P.sj_handle_info(h)
     line = {
         "metric": "batched small products GB/s (persistent per-class graph launch vs per-instance generic)",
@@ -365,10 +417,12 @@ def bench_batched(a):
                    "total_elements": total, "flops": flops},
         "roofline": {"bound": "hbm", "achieved": round(nbytes / (mean * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "sj_bgemm_persistent", "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes},
-        "graph_us_median": round(med * 1e3, 2), "generic_us": round(gmed * 1e3, 2),
+                     "kernel": info["kernel_name"], "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes},
+        "graph_us_median": round(med * 1e3, 2), "direct_launch_us_median": round(statistics.median(run_per) * 1e3, 2),
+        "generic_us": round(gmed * 1e3, 2),
         "speedup_vs_generic": round(gmed / med, 3), "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
-        "kernel_info": {k: info[k] for k in ("vgprs", "sgprs", "occupancy", "lds_bytes", "scratch_bytes", "block")},
+        "kernel_info": {k: info[k] for k in ("vgprs", "sgprs", "occupancy", "lds_bytes", "scratch_bytes", "block",
+                                             "variant", "tile_n", "unroll")},
     }
     P.sj_plan_destroy(plan)
     print(json.dumps(line), flush=True)

@@ -123,7 +123,8 @@ typedef struct sj_spec {
     int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
     int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs;
                                FP64 MFMA columns: 4-deep reduction steps per group of loads in flight
-                               (1..16); BGEMM: instances per work item (1, 2, 4, 8); 0 = default */
+                               (1..16); BGEMM: 16x16 MFMA tiles per work item (1, 2, 4, 8), each
+                               holding floor(16/n) instances of size n; 0 = default */
     int32_t  block;         /* threads per workgroup (64..1024, multiple of 64); 0 = default */
     uint32_t flags;         /* SJ_FLAG_* */
     int32_t  order;         /* DIRECT and FP64 MFMA columns: 0 = default, 1 = every workgroup walks the reduction (LTimes) or

@@ -91,11 +91,11 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
     }
     // Windows: runs of consecutive whole instances with at most `wmax` elements
     // per array.  Inside a window, instances are grouped by size class (stable)
-    // into work items of up to `u` instances.  Windows stay in memory order, so
+    // into work items of up to floor(16/n) * u instances.  Windows stay in memory order, so
     // each array is read and written as one contiguous stream.  Per window:
     //   win[8w .. 8w+7] = {first element lo, hi, element count, first meta word,
     //                      item count, meta word count, 0, 0}
-    //   meta words      = items (n | (count-1) << 5 | first offset index << 8),
+    //   meta words      = items (n | (count-1) << 5 | first offset index << 12),
     //                     then the instances' element offsets inside the window
     //                     as 16-bit values, two per word (first in the low half).
     const int64_t wmax = h->key.tile_n, u = h->key.unroll;
@@ -112,12 +112,15 @@ sj_status sj_batch_plan(sj_handle h, const int32_t *n_host, int64_t count, sj_pl
         for (int64_t i = i0; i < i1; ++i) bucket[n_host[i]].push_back(i);
         items.clear();
         lo.clear();
-        for (int n = 1; n <= 16; ++n)
-            for (size_t s0 = 0; s0 < bucket[n].size(); s0 += (size_t)u) {
-                const size_t s1 = std::min(bucket[n].size(), s0 + (size_t)u);
-                items.push_back(n | (int32_t)((s1 - s0 - 1) << 5) | (int32_t)(lo.size() << 8));
+        for (int n = 1; n <= 16; ++n) {
+            // floor(16/n) instances share one 16x16 MFMA tile; an item holds u such groups
+            const size_t chunk = (size_t)(16 / n) * (size_t)u;
+            for (size_t s0 = 0; s0 < bucket[n].size(); s0 += chunk) {
+                const size_t s1 = std::min(bucket[n].size(), s0 + chunk);
+                items.push_back(n | (int32_t)((s1 - s0 - 1) << 5) | (int32_t)(lo.size() << 12));
                 for (size_t t = s0; t < s1; ++t) lo.push_back((uint16_t)(off[(size_t)bucket[n][t]] - base));
             }
+        }
         const int64_t m0 = (int64_t)meta.size();
         meta.insert(meta.end(), items.begin(), items.end());
         for (size_t t = 0; t < lo.size(); t += 2)

@@ -88,13 +88,19 @@ def compile_all(kernel: int, base: dict, cands: list, threads: int = 8, compile_
 
 
 def tune_exhaustive(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, ptrs, dtype: int = sj.SJ_F64,
-                    cands=None, reps: int = 10, warmup: int = 2, flush=None, threads: int = 8):
+                    cands=None, reps: int = 10, warmup: int = 2, flush=None, threads: int = 8, farm=None):
     """Time every candidate on the caller's buffers ``ptrs`` (as for sj_run).
+    Compiles on host threads, or in the worker processes of ``farm`` (a
+    CompileFarm) when given.
     Returns dict(best=cand, best_ms=median, results=[(cand, median_ms, min_ms)], rejected=[...])."""
     base = dict(layout=layout, Z=Z, G=G, D=D, NM=NM, dtype=dtype)
     if cands is None:
         cands = candidates(kernel, layout, Z, G, D, NM, dtype)
-    built = compile_all(kernel, base, cands, threads)
+    if farm is not None:
+        made = farm.specialize_many([(kernel, dict(base, **c)) for c in cands])
+        built = [(c, h, err) for c, (h, _, err) in zip(cands, made)]
+    else:
+        built = compile_all(kernel, base, cands, threads)
     results, rejected = [], []
     for c, h, err in built:
         if h is None:
