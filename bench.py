@@ -166,24 +166,14 @@ def bench_moments(a):
         lib.sj_specialize(kid, sref, ctypes.byref(hout))
     hit_us = (time.perf_counter() - t0) / n_hit * 1e6
 
-    # The same from 8 host threads at once (ctypes drops the interpreter lock
-    # during the call, so the threads contend on the cache's mutex).
-    import threading
-
-    def hammer(out, idx):
-        h8 = ctypes.c_void_p()
-        r0 = time.perf_counter()
-        for _ in range(n_hit // 4):
-            lib.sj_specialize(kid, sref, ctypes.byref(h8))
-        out[idx] = (time.perf_counter() - r0) / (n_hit // 4) * 1e6
-    per_thread = [0.0] * 8
-    ths = [threading.Thread(target=hammer, args=(per_thread, i)) for i in range(8)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
-    hit_us_8 = statistics.median(per_thread)
-
+    # Native hit latency from 1 and 8 threads (a child process running the C ABI
+    # in a loop; the interpreter's own per-call cost is excluded).
+    import subprocess
+    native = {}
+    exe = os.path.join(ROOT, "paper_1904_08555_amd", "sj_lookup_bench")
+    for nt in (1, 8):
+        r = subprocess.run([exe, str(nt), "200000", "0"], capture_output=True, text=True, timeout=120)
+        native[nt] = json.loads(r.stdout)["ns_per_hit_median"] if r.returncode == 0 else None
     arrs = {}
     for lay in layouts:
         psi, phi, out = bufs[lay]
@@ -279,7 +269,7 @@ def bench_moments(a):
         zs = 2048
         done_bytes, spent = 0, 0.0
         lay_i = 0
-        while spent < a.cpu_seconds and lay_i < 200:
+        while spent < a.cpu_seconds and lay_i < 5000:
             lay = layouts[lay_i % len(layouts)]
             z0 = (lay_i * zs) % Z
             cols = gen.psi_columns(0, D, G, Z, np.repeat(np.arange(G), zs), np.tile(np.arange(z0, z0 + zs), G))
@@ -319,8 +309,9 @@ def bench_moments(a):
         "kernels": kern,
         "generic": generic,
         "jit": jit,
-        "cache_hit_us": round(hit_us, 3),
-        "cache_hit_us_8_threads": round(hit_us_8, 3),
+        "cache_hit_us_ctypes": round(hit_us, 3),
+        "cache_hit_ns_native": native[1],
+        "cache_hit_ns_native_8_threads": native[8],
         "tuned": {f"{k[1]}_{k[0]}": v for k, v in tuned.items()},
         "tune_s": None if tune_s is None else round(tune_s, 1),
         "value_default_specializations": None if default_value is None else round(default_value, 1),

@@ -33,6 +33,9 @@
  *  - Device buffers belong to the caller; the library never frees them.
  *  - Handles belong to the process-global cache; the same key always yields
  *    the same handle; a handle stays valid until sj_cache_clear() or exit.
+ *    Each thread also keeps a private front cache of the requests it made, so
+ *    a repeated sj_specialize takes no lock (measured: about 65 ns per hit
+ *    from one or eight threads).
  *    A handle is bound to the device that was current when it was created.
  *  - Plans belong to the caller (sj_plan_destroy).
  *  - Launches are asynchronous on `stream` (a hipStream_t; NULL is the null
@@ -139,7 +142,9 @@ typedef struct sj_plan_ *sj_plan;
 
 typedef struct sj_kernel_info {
     uint32_t struct_size;   /* must be sizeof(sj_kernel_info) */
-    int32_t  vgprs, agprs, sgprs;     /* from the compiler's resource-usage report (-1 if unknown) */
+    int32_t  vgprs, agprs, sgprs;     /* from the compiler's resource-usage report (-1 if unknown); for a
+                                         handle built by sj_specialize_with_code, VGPRs, LDS, scratch and
+                                         occupancy are read from the loaded function and AGPRs, SGPRs are -1 */
     int32_t  lds_bytes, scratch_bytes, occupancy;  /* occupancy: waves per SIMD (-1 if unknown) */
     int32_t  block;         /* threads per workgroup the handle launches with */
     int64_t  grid;          /* workgroups per launch (LTimes/LPlusTimes/MLP), 0 if data-dependent */
@@ -248,7 +253,10 @@ sj_status sj_handle_info(sj_handle h, sj_kernel_info *out);
 /* Code object bytes of a handle (also valid for SJ_FLAG_COMPILE_ONLY handles). */
 sj_status sj_handle_code(sj_handle h, const void **code, size_t *size);
 sj_status sj_stats(sj_stats_t *out);
-/* Drop every cache entry and unload its module.  No handle may be in use. */
+/* Drop every cache entry and unload its module.  No handle may be in use, and
+ * no other call of this library may run concurrently (a lookup racing with the
+ * clear could return a handle that is being freed).  Every thread's private
+ * front cache is emptied at its next lookup. */
 sj_status sj_cache_clear(void);
 const char *sj_last_error(void);
 const char *sj_status_string(sj_status s);

@@ -3,13 +3,15 @@
 //
 // Cache (ClangJIT section 4, Algorithm 1: look the instantiation up, build it
 // on a miss, store it, return it): an unordered_map from the canonical key to
-// an entry, under one mutex.  A miss inserts a "building" entry and compiles
-// outside the lock; concurrent requests for the same key wait for that entry
-// instead of compiling again.  A failed build removes its entry, so a later
-// request retries.  The paper reports that the lookup itself is what costs
+// an entry.  A hit takes only a shared (reader) lock on the map, so hits from
+// many threads proceed together; a miss takes the build mutex, inserts a
+// "building" entry and compiles outside every lock; concurrent requests for
+// the same key wait for that entry instead of compiling again.  A failed
+// build removes its entry, so a later request retries.  The paper reports that the lookup itself is what costs
 // (section 5.1); here the lookup happens once, in sj_specialize, and sj_run
 // launches from the handle without touching the cache.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -17,8 +19,10 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "sj_internal.h"
 
@@ -29,23 +33,108 @@ namespace {
 enum EntryState { kBuilding = 0, kReady = 1, kFailed = 2 };
 
 struct Entry {
-    int state = kBuilding;
+    std::atomic<int> state{kBuilding};   // h is set before state becomes kReady (release)
     sj_handle_ *h = nullptr;
     sj_status err = SJ_OK;
     std::string msg;
 };
 
-std::mutex g_mu;
+// Lock order: g_mu, then g_rw.  Map insertions and removals hold both; hits
+// hold g_rw shared only; the miss path reads the map under g_mu.
+std::mutex g_mu;                 // builds, statistics, the in-flight condition
+std::shared_mutex g_rw;          // the map's structure
 std::condition_variable g_cv;
 std::unordered_map<SpecKey, std::shared_ptr<Entry>, KeyHashF, KeyEqF> g_map;
 sj_stats_t g_stats{};
+std::atomic<uint64_t> g_lookups{0}, g_hits{0};
 
 struct DeviceState {
-    bool ready = false;
+    std::atomic<bool> ready{false};   // arch is written before ready (release)
     std::string arch;
 };
 std::mutex g_dev_mu;
 DeviceState g_dev[64];
+
+// Per-thread front cache: the caller's request as given (kernel, device and
+// the spec's fields with padding zeroed) -> handle.  A hit costs one hash and
+// one compare of 15 words, takes no lock and writes no shared cache line.
+// make_key is a pure function of exactly these inputs, so a front hit returns
+// the handle the canonical cache would.  sj_cache_clear bumps g_epoch, which
+// empties every thread's front cache at its next lookup.
+struct RawKey {
+    int32_t kernel, device, dtype, layout, variant, pad0;
+    int64_t Z, G, D, NM, count;
+    uint32_t class_mask;
+    int32_t tile_n, tile_k, unroll, block;
+    uint32_t flags;
+    int32_t order, pad1;
+    int64_t rows, inputs, width;
+};
+static_assert(sizeof(RawKey) % 8 == 0, "raw key is hashed as 64-bit words");
+
+RawKey raw_key(sj_kernel k, const sj_spec *s, int device)
+{
+    RawKey r;
+    std::memset(&r, 0, sizeof r);
+    r.kernel = k;
+    r.device = device;
+    r.dtype = s->dtype;
+    r.layout = s->layout;
+    r.variant = s->variant;
+    r.Z = s->Z;
+    r.G = s->G;
+    r.D = s->D;
+    r.NM = s->NM;
+    r.count = s->count;
+    r.class_mask = s->class_mask;
+    r.tile_n = s->tile_n;
+    r.tile_k = s->tile_k;
+    r.unroll = s->unroll;
+    r.block = s->block;
+    r.flags = s->flags;
+    r.order = s->order;
+    r.rows = s->rows;
+    r.inputs = s->inputs;
+    r.width = s->width;
+    return r;
+}
+
+struct RawHashF {
+    size_t operator()(const RawKey &k) const { return (size_t)hash_words(&k, sizeof k); }
+};
+struct RawEqF {
+    bool operator()(const RawKey &a, const RawKey &b) const { return std::memcmp(&a, &b, sizeof a) == 0; }
+};
+
+struct FrontCounter {
+    std::atomic<uint64_t> hits{0};   // written by its thread only; summed by sj_stats
+};
+std::mutex g_front_mu;
+std::vector<FrontCounter *> g_front;   // one per thread that looked anything up; never freed
+std::atomic<uint64_t> g_epoch{0};
+
+struct FrontCache {
+    uint64_t epoch = ~0ull;
+    FrontCounter *counter = nullptr;
+    std::unordered_map<RawKey, sj_handle_ *, RawHashF, RawEqF> map;
+};
+thread_local FrontCache t_front;
+
+FrontCache &front()
+{
+    FrontCache &f = t_front;
+    if (!f.counter) {
+        f.counter = new FrontCounter;
+        std::lock_guard<std::mutex> lk(g_front_mu);
+        g_front.push_back(f.counter);
+    }
+    const uint64_t ep = g_epoch.load(std::memory_order_acquire);
+    if (f.epoch != ep) {
+        f.map.clear();
+        f.epoch = ep;
+    }
+    return f;
+}
 
 double ms_since(std::chrono::steady_clock::time_point t0)
 {
@@ -62,13 +151,10 @@ sj_status ensure_device(int *device, const char **arch)
         return fail(SJ_ERR_NOT_INITIALIZED, "no HIP device is available");
     }
     if (dev < 0 || dev >= 64) return fail(SJ_ERR_UNSUPPORTED, "device ordinal beyond 63");
-    {
-        std::lock_guard<std::mutex> lk(g_dev_mu);
-        if (g_dev[dev].ready) {
-            *device = dev;
-            *arch = g_dev[dev].arch.c_str();
-            return SJ_OK;
-        }
+    if (g_dev[dev].ready.load(std::memory_order_acquire)) {
+        *device = dev;
+        *arch = g_dev[dev].arch.c_str();
+        return SJ_OK;
     }
     sj_status s = (sj_status)sj_init(dev);
     if (s != SJ_OK) return s;
@@ -138,6 +224,16 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
         }
         h->info.load_ms = ms_since(t0);
         h->runnable = true;
+        if (precompiled) {
+            // resource usage of a code object compiled elsewhere, from the loaded function
+            int v = 0;
+            if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_NUM_REGS, h->fn) == hipSuccess) h->info.vgprs = v;
+            if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, h->fn) == hipSuccess) h->info.lds_bytes = v;
+            if (hipFuncGetAttribute(&v, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, h->fn) == hipSuccess) h->info.scratch_bytes = v;
+            int blocks = 0;
+            if (h->geom.block && hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, h->fn, (int)h->geom.block, 0) == hipSuccess)
+                h->info.occupancy = (int32_t)std::min<int64_t>(8, (int64_t)blocks * (h->geom.block / 64) / 4);
+        }
         std::lock_guard<std::mutex> lk(g_mu);
         g_stats.loads++;
         g_stats.load_ms_total += h->info.load_ms;
@@ -148,20 +244,29 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
 
 sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<char> *precompiled = nullptr)
 {
+    g_lookups.fetch_add(1, std::memory_order_relaxed);
+    {   // hit: shared lock only
+        std::shared_lock<std::shared_mutex> rl(g_rw);
+        auto it = g_map.find(key);
+        if (it != g_map.end() && it->second->state.load(std::memory_order_acquire) == kReady) {
+            g_hits.fetch_add(1, std::memory_order_relaxed);
+            *out = it->second->h;
+            return SJ_OK;
+        }
+    }
     std::unique_lock<std::mutex> lk(g_mu);
-    g_stats.lookups++;
     auto it = g_map.find(key);
     if (it != g_map.end()) {
         std::shared_ptr<Entry> e = it->second;
-        if (e->state == kReady) {
-            g_stats.hits++;
+        if (e->state.load(std::memory_order_acquire) == kReady) {
+            g_hits.fetch_add(1, std::memory_order_relaxed);
             *out = e->h;
             return SJ_OK;
         }
         g_stats.inflight_waits++;
-        g_cv.wait(lk, [&] { return e->state != kBuilding; });
-        if (e->state == kReady) {
-            g_stats.hits++;
+        g_cv.wait(lk, [&] { return e->state.load(std::memory_order_acquire) != kBuilding; });
+        if (e->state.load(std::memory_order_acquire) == kReady) {
+            g_hits.fetch_add(1, std::memory_order_relaxed);
             *out = e->h;
             return SJ_OK;
         }
@@ -169,7 +274,10 @@ sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<c
     }
     g_stats.misses++;
     auto e = std::make_shared<Entry>();
-    g_map.emplace(key, e);
+    {
+        std::unique_lock<std::shared_mutex> wl(g_rw);
+        g_map.emplace(key, e);
+    }
     lk.unlock();
 
     sj_handle_ *h = nullptr;
@@ -178,13 +286,14 @@ sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<c
 
     lk.lock();
     if (s == SJ_OK) {
-        e->state = kReady;
         e->h = h;
+        e->state.store(kReady, std::memory_order_release);
         g_stats.entries++;
     } else {
-        e->state = kFailed;
         e->err = s;
         e->msg = msg;
+        e->state.store(kFailed, std::memory_order_release);
+        std::unique_lock<std::shared_mutex> wl(g_rw);
         g_map.erase(key);
     }
     lk.unlock();
@@ -246,12 +355,12 @@ sj_status sj_init(int hip_device)
         return fail(SJ_ERR_NOT_INITIALIZED, "HIP device not present");
     }
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    if (g_dev[hip_device].ready) return SJ_OK;
+    if (g_dev[hip_device].ready.load(std::memory_order_acquire)) return SJ_OK;
     if (hipSetDevice(hip_device) != hipSuccess) return fail(SJ_ERR_HIP, "hipSetDevice failed");
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return fail(SJ_ERR_HIP, "hipGetDeviceProperties failed");
     g_dev[hip_device].arch = prop.gcnArchName;
-    g_dev[hip_device].ready = true;
+    g_dev[hip_device].ready.store(true, std::memory_order_release);
     return SJ_OK;
 }
 
@@ -289,12 +398,23 @@ sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out)
         sj_status s = ensure_device(&device, &arch);
         if (s != SJ_OK) return s;
     }
+    if (spec->struct_size != sizeof(sj_spec)) return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size mismatch");
+    FrontCache &f = front();
+    const RawKey rk = raw_key(k, spec, device);
+    auto fit = f.map.find(rk);
+    if (fit != f.map.end()) {
+        f.counter->hits.fetch_add(1, std::memory_order_relaxed);
+        *out = fit->second;
+        return SJ_OK;
+    }
     SpecKey key;
     sj_status s = make_key(k, spec, device, arch, &key);
     if (s != SJ_OK) return s;
     sj_handle_ *h = nullptr;
     s = get_or_build(key, &h);
     if (s != SJ_OK) return s;
+    if (f.map.size() >= 4096) f.map.clear();   // bounded: a thread cycling through many keys
+    f.map.emplace(rk, h);
     *out = h;
     return SJ_OK;
 }
@@ -475,6 +595,13 @@ sj_status sj_stats(sj_stats_t *out)
     if (out->struct_size != sizeof(sj_stats_t)) return fail(SJ_ERR_INVALID_ARG, "sj_stats_t.struct_size mismatch");
     std::lock_guard<std::mutex> lk(g_mu);
     *out = g_stats;
+    uint64_t front_hits = 0;
+    {
+        std::lock_guard<std::mutex> fl(g_front_mu);
+        for (FrontCounter *c : g_front) front_hits += c->hits.load(std::memory_order_relaxed);
+    }
+    out->lookups = g_lookups.load(std::memory_order_relaxed) + front_hits;
+    out->hits = g_hits.load(std::memory_order_relaxed) + front_hits;
     out->struct_size = sizeof(sj_stats_t);
     return SJ_OK;
 }
@@ -482,8 +609,10 @@ sj_status sj_stats(sj_stats_t *out)
 sj_status sj_cache_clear(void)
 {
     std::unique_lock<std::mutex> lk(g_mu);
+    std::unique_lock<std::shared_mutex> wl(g_rw);
     for (auto &kv : g_map)
-        if (kv.second->state == kBuilding) return fail(SJ_ERR_INVALID_ARG, "a specialization is being compiled");
+        if (kv.second->state.load(std::memory_order_acquire) == kBuilding)
+            return fail(SJ_ERR_INVALID_ARG, "a specialization is being compiled");
     for (auto &kv : g_map) {
         sj_handle_ *h = kv.second->h;
         if (h) {
@@ -493,6 +622,7 @@ sj_status sj_cache_clear(void)
     }
     g_map.clear();
     g_stats.entries = 0;
+    g_epoch.fetch_add(1, std::memory_order_acq_rel);   // every thread's front cache empties at its next lookup
     return SJ_OK;
 }
 

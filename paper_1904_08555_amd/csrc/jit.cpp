@@ -52,14 +52,35 @@ namespace sj {
 
 bool key_equal(const SpecKey &a, const SpecKey &b) { return std::memcmp(&a, &b, sizeof(SpecKey)) == 0; }
 
+uint64_t hash_words(const void *p, size_t bytes)
+{
+    // Two independent multiply-rotate chains over the 64-bit words, joined by
+    // one final mix (the chains overlap in the pipeline; a single chained mix
+    // per word was a third of a cache hit's time).
+    const size_t n = bytes / 8;
+    uint64_t a = 0x243F6A8885A308D3ull, b = 0x13198A2E03707344ull;
+    size_t i = 0;
+    for (; i + 1 < n; i += 2) {
+        uint64_t w0, w1;
+        std::memcpy(&w0, (const char *)p + 8 * i, 8);
+        std::memcpy(&w1, (const char *)p + 8 * i + 8, 8);
+        a = ((a ^ w0) * 0x9E3779B97F4A7C15ull);
+        a = (a << 29) | (a >> 35);
+        b = ((b ^ w1) * 0xC2B2AE3D27D4EB4Full);
+        b = (b << 31) | (b >> 33);
+    }
+    if (i < n) {
+        uint64_t w0;
+        std::memcpy(&w0, (const char *)p + 8 * i, 8);
+        a = ((a ^ w0) * 0x9E3779B97F4A7C15ull);
+    }
+    return mix64(a ^ ((b << 17) | (b >> 47)) ^ (uint64_t)bytes);
+}
+
 uint64_t key_hash(const SpecKey &k)
 {
     static_assert(sizeof(SpecKey) % 8 == 0, "key is hashed as 64-bit words");
-    uint64_t w[sizeof(SpecKey) / 8];
-    std::memcpy(w, &k, sizeof(SpecKey));
-    uint64_t h = 0x243F6A8885A308D3ull;
-    for (size_t i = 0; i < sizeof(SpecKey) / 8; ++i) h = mix64(h ^ w[i]) + 0x9E3779B97F4A7C15ull;
-    return h;
+    return hash_words(&k, sizeof(SpecKey));
 }
 
 // ---------------------------------------------------------------- layouts

@@ -30,6 +30,7 @@ struct SpecKey {
 
 bool key_equal(const SpecKey &a, const SpecKey &b);
 uint64_t key_hash(const SpecKey &k);
+uint64_t hash_words(const void *p, size_t bytes);   // bytes a multiple of 8
 
 struct KeyHashF {
     size_t operator()(const SpecKey &k) const { return (size_t)key_hash(k); }
