@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--tile", default="", help="override tile params, e.g. 'tile_n=2,unroll=8,block=256'")
     ap.add_argument("--no-tune", action="store_true",
                     help="moments: time the default specializations only (no exhaustive tuning first)")
+    ap.add_argument("--tuned-json", default="",
+                    help="moments: take the tuned specializations from this file (written by an earlier run to "
+                         "gpurun_out/tuned_moments.json) instead of tuning")
     ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
@@ -126,7 +129,13 @@ def bench_moments(a):
 
     # --- exhaustive tuning on the resident buffers (compiles in worker processes) ----------
     tuned, tune_s = {}, None
-    if not a.no_tune and not tile:
+    if a.tuned_json:
+        with open(a.tuned_json) as f:
+            for k, v in json.load(f).items():
+                kname, lay = k.split("_")
+                if lay in layouts:
+                    tuned[(lay, kname)] = v
+    elif not a.no_tune and not tile:
         from paper_1904_08555_amd import tune
         from paper_1904_08555_amd.farm import CompileFarm
         t0 = time.perf_counter()
@@ -140,6 +149,9 @@ def bench_moments(a):
                     print(f"tuned {kname} {lay}: {r['best']} {r['best_ms'] * 1e3:.1f} us "
                           f"({len(r['results'])} candidates)", file=sys.stderr, flush=True)
         tune_s = time.perf_counter() - t0
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(ROOT, "gpurun_out", "tuned_moments.json"), "w") as f:
+            json.dump({f"{k[1]}_{k[0]}": v for k, v in tuned.items()}, f)
     for lay in layouts:
         for kname, kid in (("ltimes", P.SJ_LTIMES), ("lplustimes", P.SJ_LPLUSTIMES)):
             s = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **(tuned.get((lay, kname)) or tile))
@@ -220,9 +232,10 @@ def bench_moments(a):
         ms = statistics.median(per_kernel[key])
         kern[f"{key[1]}_{key[0]}"] = dict(us=round(ms * 1e3, 2), gbs=round(nbytes / (ms * 1e-3) / 1e9, 1),
                                            frac=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
-    # the same step with the default (untuned) specializations
+    # the same step with the default (untuned) specializations (skipped when the
+    # tuned choices come from a file, as in a profiled run)
     default_value = None
-    if tuned:
+    if tuned and not a.tuned_json:
         for _ in range(a.warmup):
             step(table=default_specs)
         torch.cuda.synchronize()

@@ -111,7 +111,9 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
     key.device = device;
     key.lib_version = SJ_VERSION;
     std::snprintf(key.arch, sizeof key.arch, "%s", arch ? arch : "");
-    key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE);
+    key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE | SJ_FLAG_CACHED | SJ_FLAG_NONTEMPORAL);
+    if ((s->flags & SJ_FLAG_CACHED) && (s->flags & SJ_FLAG_NONTEMPORAL))
+        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_CACHED and SJ_FLAG_NONTEMPORAL exclude each other");
 
     if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
         if (s->layout < SJ_DGZ || s->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
@@ -377,7 +379,13 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
         o << "#define SJ_BLOCK " << k.block << "\n";
         // streaming hint: skip cache retention when every fetched line is used at once
-        const int nt = (k.variant != SJ_VAR_DIRECT) ? 1 : (k.I * (k.tile_n ? k.tile_n : 1) >= 16 ? 1 : 0);
+        // load/store policy: explicit flag, else the structure's default (measured on MI355X)
+        int nt;
+        if (k.flags & SJ_FLAG_CACHED) nt = 0;
+        else if (k.flags & SJ_FLAG_NONTEMPORAL) nt = 1;
+        else if (k.variant == SJ_VAR_DIRECT) nt = (k.I * (k.tile_n ? k.tile_n : 1) >= 16) ? 1 : 0;
+        else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1) nt = 0;   // row kernel
+        else nt = 1;
         o << "#define SJ_NT " << nt << "\n";
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "

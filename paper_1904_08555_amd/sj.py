@@ -50,6 +50,8 @@ SJ_VAR_MFMA = 3
 # flags
 SJ_FLAG_COMPILE_ONLY = 0x1
 SJ_FLAG_INDEX64 = 0x2
+SJ_FLAG_CACHED = 0x4
+SJ_FLAG_NONTEMPORAL = 0x8
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 
 EXPORTED = (

@@ -260,3 +260,23 @@ def test_bgemm_prefetch_form(P):
     with pytest.raises(P.SJError) as e:
         P.sj_specialize(P.SJ_BGEMM, tile_n=7169, flags=P.SJ_FLAG_COMPILE_ONLY)
     assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+def test_load_store_policy_flags(P):
+    """The streamed-operand policy: the structure's default, or an explicit
+    flag, which is part of the key; the two flags exclude each other."""
+    base = dict(Z=4096, G=8, D=48, NM=16, flags=P.SJ_FLAG_COMPILE_ONLY)
+    assert "#define SJ_NT 0" in P.sj_emit_source(P.SJ_LTIMES, layout="ZGD", variant=P.SJ_VAR_MFMA, **base)
+    assert "#define SJ_NT 1" in P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", **base)
+    src = P.sj_emit_source(P.SJ_LTIMES, layout="ZGD", variant=P.SJ_VAR_MFMA,
+                           **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_NONTEMPORAL))
+    assert "#define SJ_NT 1" in src
+    src = P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED))
+    assert "#define SJ_NT 0" in src
+    h0 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", **base)
+    h1 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED))
+    assert h0 != h1
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_LTIMES, layout="DGZ",
+                        **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED | P.SJ_FLAG_NONTEMPORAL))
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
