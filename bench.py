@@ -35,6 +35,29 @@ HBM_PEAK_GBS = 8000.0
 LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 
 
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch;
+# both factors from a 1 GiB device copy), keyed by the SHA-1 of the emitted kernel source the counters
+# were taken on: a kernel whose source has changed since reports traffic null.  The summaries with the
+# commands are the *_hbm_counters.md and bgemm_*_counters.md files under profiles/.
+MEASURED_TRAFFIC = {
+    # LTimes ZGD, Z=32768 G=32 D=96 NM=16, FP64 MFMA rows, tile_n 2, block 256, ordinary loads
+    "43a31569646b5a5603f8824a8fa578f85da6b09d": (393305 * 2 + 131072) * 1024,
+    # LPlusTimes ZGD, same shape, MFMA rows, tile_n 2, block 512, nontemporal
+    "17895bfb76d06a63c9b3cbcc4231444398228b5f": (66606 * 2 + 786621) * 1024,
+    # LTimes / LPlusTimes DGZ, same shape, FP64 MFMA columns, tile_n 2, unroll 8
+    "adcaa487244ce6230680886385d1d35cfd2a96b2": (393303 * 2 + 131072) * 1024,
+    "2ca0cf222c7d6d4c16fd12d643f88e422a9e712b": (65626 * 2 + 786709) * 1024,
+    # batched products, 200,000 instances, default specialization
+    "137a01fa3f26d08483c506090e188ed1e385e877": (172659 * 2 + 176083) * 1024,
+}
+
+
+def measured_traffic(P, kernel, spec):
+    """HBM bytes per launch from the counters if they were taken on this exact kernel source, else None."""
+    import hashlib
+    return MEASURED_TRAFFIC.get(hashlib.sha1(P.sj_emit_source(kernel, spec).encode()).hexdigest())
+
+
 def algorithmic_bytes(Z, G, D, NM, esz=8):
     """Each operand read once, each result written once (LTimes or LPlusTimes)."""
     return (D + NM) * G * Z * esz + NM * D * 8
@@ -315,7 +338,7 @@ def bench_moments(a):
                    "specialization": ("chosen per nesting and kernel by the exhaustive tuner before the timed region"
                                       if tuned else "library defaults")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, *specs[dom]),
                      "kernel": f"{dom[1]}_{dom[0]}", "avg_us": round(dom_ms * 1e3, 2),
                      "bytes_per_launch": nbytes},
         "cpu_baseline": cpu,
@@ -401,8 +424,9 @@ def bench_batched(a):
 
     per, t_total = flushed(lambda: P.sj_batch_graph_launch(plan), a.steps)
     med = statistics.median(per)
-    mean = statistics.mean(per)
-    run_per, _ = flushed(lambda: P.sj_batch_run(plan, A_d, B_d, C_d), max(3, a.steps // 2))
+    # the kernel's own duration: events around direct launches (a graph replay adds launch latency)
+    run_per, _ = flushed(lambda: P.sj_batch_run(plan, A_d, B_d, C_d), a.steps)
+    mean = statistics.mean(run_per)
     n_dev, off_dev, _ = P.sj_batch_plan_arrays(plan)
     gspec = P.make_spec(count=count)
 
@@ -420,7 +444,8 @@ def bench_batched(a):
         "config": {"workload": "200000 products, n ~ U{3..16}, A,B ~ N(0,1), FP64, packed row-major",
                    "total_elements": total, "flops": flops},
         "roofline": {"bound": "hbm", "achieved": round(nbytes / (mean * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(P, P.SJ_BGEMM, P.make_spec(**tile)),
                      "kernel": info["kernel_name"], "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes},
         "graph_us_median": round(med * 1e3, 2), "direct_launch_us_median": round(statistics.median(run_per) * 1e3, 2),
         "generic_us": round(gmed * 1e3, 2),
