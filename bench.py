@@ -91,7 +91,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}); "
+        print(f"bench.py runs on one GPU: this library has no multi-GPU path (asked for --gpus {a.gpus}); "
               "the contractions are independent per (g, z) column, so N GPUs would each run the one-GPU kernel "
               "on a zone shard.", file=sys.stderr)
         sys.exit(2)
