@@ -151,7 +151,7 @@ def bench_moments(a):
             default_specs[(lay, kname)] = (kid, P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **tile))
 
     # --- exhaustive tuning on the resident buffers (compiles in worker processes) ----------
-    tuned, tune_s = {}, None
+    tuned, tune_s, ranked = {}, None, {}
     if a.tuned_json:
         with open(a.tuned_json) as f:
             for k, v in json.load(f).items():
@@ -169,6 +169,7 @@ def bench_moments(a):
                                          ("lplustimes", P.SJ_LPLUSTIMES, [Lp_d, phi, out])):
                     r = tune.tune_exhaustive(kid, lay, Z, G, D, NM, ptrs, reps=10, warmup=2, farm=farm)
                     tuned[(lay, kname)] = r["best"]
+                    ranked[(lay, kname)] = [c for c, _, _ in sorted(r["results"], key=lambda x: x[1])[:3]]
                     print(f"tuned {kname} {lay}: {r['best']} {r['best_ms'] * 1e3:.1f} us "
                           f"({len(r['results'])} candidates)", file=sys.stderr, flush=True)
         tune_s = time.perf_counter() - t0
@@ -178,18 +179,9 @@ def bench_moments(a):
     for lay in layouts:
         for kname, kid in (("ltimes", P.SJ_LTIMES), ("lplustimes", P.SJ_LPLUSTIMES)):
             s = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **(tuned.get((lay, kname)) or tile))
-            t0 = time.perf_counter()
             h = P.sj_specialize(kid, s)
-            wall = (time.perf_counter() - t0) * 1e3
-            info = P.sj_handle_info(h)
             specs[(lay, kname)] = (kid, s)
             handles[(lay, kname)] = h
-            jit[f"{kname}_{lay}"] = dict(wall_ms=round(wall, 1), emit_ms=round(info["emit_ms"], 3),
-                                     compile_ms=round(info["compile_ms"], 1), load_ms=round(info["load_ms"], 2),
-                                     vgprs=info["vgprs"], sgprs=info["sgprs"], scratch=info["scratch_bytes"],
-                                     occupancy=info["occupancy"], lds=info["lds_bytes"], kernel=info["kernel_name"],
-                                     variant=info["variant"], tile_n=info["tile_n"], tile_k=info["tile_k"],
-                                     unroll=info["unroll"], block=info["block"])
 
     # Cache-hit latency of sj_specialize (through ctypes, so an upper bound).
     hout = ctypes.c_void_p()
@@ -230,6 +222,59 @@ def bench_moments(a):
                 events[key][1].record(stream)
             if rc != 0:
                 raise RuntimeError(P.sj_last_error())
+
+    # In-step refinement of the tuned choices: a kernel's speed depends on the one
+    # before it (the previous LPlusTimes' writes are still draining when the next
+    # LTimes starts), which the isolated tuning cannot see.  Each kernel in turn
+    # tries its three best isolated candidates inside the whole step and keeps the
+    # one with the lowest median step time.
+    refined = 0
+    if ranked:
+        def step_ms(reps=5):
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                step()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return statistics.median(ts) * 1e3
+        for key in order:
+            kid = specs[key][0]
+            lay = key[0]
+            best_spec, best_t = specs[key], step_ms()
+            for c in ranked.get(key, [])[1:]:
+                specs[key] = (kid, P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, **c))
+                t = step_ms()
+                if t < best_t:
+                    best_spec, best_t = specs[key], t
+                    tuned[key] = c
+                    refined += 1
+            specs[key] = best_spec
+        with open(os.path.join(ROOT, "gpurun_out", "tuned_moments.json"), "w") as f:
+            json.dump({f"{k[1]}_{k[0]}": v for k, v in tuned.items()}, f)
+
+    # the specializations the timed steps use (after any refinement)
+    for key in order:
+        kid, s = specs[key]
+        info = P.sj_handle_info(P.sj_specialize(kid, s))
+        jit[f"{key[1]}_{key[0]}"] = dict(kernel=info["kernel_name"], variant=info["variant"], tile_n=info["tile_n"],
+                                         tile_k=info["tile_k"], unroll=info["unroll"], block=info["block"],
+                                         vgprs=info["vgprs"], scratch=info["scratch_bytes"],
+                                         occupancy=info["occupancy"], lds=info["lds_bytes"])
+    # cold specialization cost: ten keys never compiled before, in this process
+    cold = []
+    for i in range(10):
+        kid_c = P.SJ_LTIMES if i % 2 == 0 else P.SJ_LPLUSTIMES
+        t0 = time.perf_counter()
+        hc = P.sj_specialize(kid_c, layout=layouts[i % len(layouts)], Z=Z + 64 * (i + 1), G=G, D=D, NM=NM)
+        wall = (time.perf_counter() - t0) * 1e3
+        ic = P.sj_handle_info(hc)
+        cold.append((wall, ic["emit_ms"], ic["compile_ms"], ic["load_ms"]))
+    jit_cold = {name: round(statistics.median(x[j] for x in cold), 3)
+                for j, name in enumerate(("wall_ms", "emit_ms", "compile_ms", "load_ms"))}
 
     for _ in range(a.warmup):
         step()
@@ -345,11 +390,13 @@ def bench_moments(a):
         "kernels": kern,
         "generic": generic,
         "jit": jit,
+        "jit_cold_median_of_10_keys": jit_cold,
         "cache_hit_us_ctypes": round(hit_us, 3),
         "cache_hit_ns_native": native[1],
         "cache_hit_ns_native_8_threads": native[8],
         "tuned": {f"{k[1]}_{k[0]}": v for k, v in tuned.items()},
         "tune_s": None if tune_s is None else round(tune_s, 1),
+        "refined_in_step": refined,
         "value_default_specializations": None if default_value is None else round(default_value, 1),
     }
     print(json.dumps(line), flush=True)

@@ -109,12 +109,15 @@ typedef enum sj_variant {
 /* Flags. */
 #define SJ_FLAG_COMPILE_ONLY      0x1u  /* compile to a code object, do not load: no GPU needed; the handle cannot run */
 #define SJ_FLAG_INDEX64           0x2u  /* force 64-bit indexing (chosen automatically when an array has >= 2^31 elements) */
-#define SJ_FLAG_CACHED            0x4u  /* LTimes / LPlusTimes: ordinary loads and stores */
-#define SJ_FLAG_NONTEMPORAL       0x8u  /* LTimes / LPlusTimes: nontemporal loads and stores.  With neither flag the
-                                           structure's default applies (measured on MI355X): nontemporal for the
-                                           column kernels (DIRECT over >= 16 contiguous values, FP64 and BF16 MFMA
-                                           columns), ordinary for the FP64 MFMA row kernel, whose lanes read each
-                                           128-byte line in two halves from two instructions.  Both flags: invalid. */
+#define SJ_FLAG_LOADS_CACHED      0x4u  /* LTimes / LPlusTimes: ordinary loads of the streamed input */
+#define SJ_FLAG_LOADS_NONTEMPORAL 0x8u  /* LTimes / LPlusTimes: nontemporal loads of the streamed input */
+#define SJ_FLAG_STORES_CACHED     0x10u /* LTimes / LPlusTimes: ordinary stores of the output */
+#define SJ_FLAG_STORES_NONTEMPORAL 0x20u /* LTimes / LPlusTimes: nontemporal stores of the output */
+/* Without a loads flag (stores flag) the default measured on MI355X applies:
+ * nontemporal stores for every streamed output; nontemporal loads for LTimes'
+ * column kernels, ordinary loads for LPlusTimes and for the FP64 MFMA row
+ * kernel.  The two flags of a pair exclude each other; every policy flag is
+ * part of the specialization key. */
 #define SJ_FLAG_DEBUG_FAIL_COMPILE 0x100u /* test hook: the emitted source contains a failing static_assert */
 
 typedef struct sj_spec {

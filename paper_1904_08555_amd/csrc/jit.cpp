@@ -111,9 +111,12 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
     key.device = device;
     key.lib_version = SJ_VERSION;
     std::snprintf(key.arch, sizeof key.arch, "%s", arch ? arch : "");
-    key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE | SJ_FLAG_CACHED | SJ_FLAG_NONTEMPORAL);
-    if ((s->flags & SJ_FLAG_CACHED) && (s->flags & SJ_FLAG_NONTEMPORAL))
-        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_CACHED and SJ_FLAG_NONTEMPORAL exclude each other");
+    key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE | SJ_FLAG_LOADS_CACHED |
+                            SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED | SJ_FLAG_STORES_NONTEMPORAL);
+    if ((s->flags & SJ_FLAG_LOADS_CACHED) && (s->flags & SJ_FLAG_LOADS_NONTEMPORAL))
+        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_LOADS_CACHED and SJ_FLAG_LOADS_NONTEMPORAL exclude each other");
+    if ((s->flags & SJ_FLAG_STORES_CACHED) && (s->flags & SJ_FLAG_STORES_NONTEMPORAL))
+        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_STORES_CACHED and SJ_FLAG_STORES_NONTEMPORAL exclude each other");
 
     if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
         if (s->layout < SJ_DGZ || s->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
@@ -354,11 +357,14 @@ Geometry key_geometry(const SpecKey &k)
 
 static const char *kCommonPrologue =
     "// emitted by the sj specializer\n"
-    "#if SJ_NT\n"
+    "#if SJ_NT_LOAD\n"
     "#define SJ_LOAD(p) __builtin_nontemporal_load(p)\n"
-    "#define SJ_STORE(v, p) __builtin_nontemporal_store((v), (p))\n"
     "#else\n"
     "#define SJ_LOAD(p) (*(p))\n"
+    "#endif\n"
+    "#if SJ_NT_STORE\n"
+    "#define SJ_STORE(v, p) __builtin_nontemporal_store((v), (p))\n"
+    "#else\n"
     "#define SJ_STORE(v, p) (*(p) = (v))\n"
     "#endif\n";
 
@@ -379,14 +385,20 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
         o << "#define SJ_BLOCK " << k.block << "\n";
         // streaming hint: skip cache retention when every fetched line is used at once
-        // load/store policy: explicit flag, else the structure's default (measured on MI355X)
-        int nt;
-        if (k.flags & SJ_FLAG_CACHED) nt = 0;
-        else if (k.flags & SJ_FLAG_NONTEMPORAL) nt = 1;
-        else if (k.variant == SJ_VAR_DIRECT) nt = (k.I * (k.tile_n ? k.tile_n : 1) >= 16) ? 1 : 0;
-        else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1) nt = 0;   // row kernel
-        else nt = 1;
-        o << "#define SJ_NT " << nt << "\n";
+        // Load and store policy: explicit flags, else the default measured on MI355X at
+        // Z=32768 G=32 D=96 NM=16: nontemporal stores for every streamed output;
+        // nontemporal loads only for LTimes' column kernels (LTimes DGZ 166 us vs 177 us with
+        // ordinary loads); ordinary loads for LPlusTimes (DGZ 151 us vs 186 us nontemporal) and
+        // for the row kernel, whose lanes read each 128-byte line in two halves (171 us vs 199 us).
+        const bool rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1);
+        const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
+        int ntl = (k.kernel == SJ_LTIMES && streamed && !rows) ? 1 : 0;
+        int nts = streamed ? 1 : 0;
+        if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
+        if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
+        if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
+        if (k.flags & SJ_FLAG_STORES_NONTEMPORAL) nts = 1;
+        o << "#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n";
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
               << k.full_unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
@@ -417,7 +429,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
     }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {
         o << "#define SJ_R " << k.rows << "\n#define SJ_F " << (k.inputs ? k.inputs : 1) << "\n#define SJ_H "
-          << (k.width ? k.width : 1) << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT 0\n"
+          << (k.width ? k.width : 1) << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n"
           << "#define SJ_WANT_FWD " << (k.kernel == SJ_MLP_FWD) << "\n#define SJ_WANT_BWD " << (k.kernel == SJ_MLP_BWD)
           << "\n#define SJ_WANT_ADAM " << (k.kernel == SJ_ADAM) << "\n";
         body = kTpl_mlp;
@@ -437,7 +449,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
                 o << " case " << n << ": it = sj_bgemm_class<" << n << ">(Ms, Ls, it, nitems, As, Bs); break;";
-        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT 0\n";
+        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n";
         bgemm_common = kTpl_bgemm_common;
         body = wave_form ? kTpl_bgemm_wave : kTpl_bgemm;
         *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";

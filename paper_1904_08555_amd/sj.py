@@ -50,8 +50,10 @@ SJ_VAR_MFMA = 3
 # flags
 SJ_FLAG_COMPILE_ONLY = 0x1
 SJ_FLAG_INDEX64 = 0x2
-SJ_FLAG_CACHED = 0x4
-SJ_FLAG_NONTEMPORAL = 0x8
+SJ_FLAG_LOADS_CACHED = 0x4
+SJ_FLAG_LOADS_NONTEMPORAL = 0x8
+SJ_FLAG_STORES_CACHED = 0x10
+SJ_FLAG_STORES_NONTEMPORAL = 0x20
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 
 EXPORTED = (

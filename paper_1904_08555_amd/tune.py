@@ -16,8 +16,8 @@ The candidate set (at most 33 per kernel and layout):
     loads) in {2, 4, 8}, default order  (<= 9)
   * innermost axis is D (GZD, ZGD): STAGED with tile_k in {8, 16, 32},
     block 256, tile_n in {256, 512}; FP64 MFMA with 16-row tiles per wave in
-    {1, 2, 4}, block in {256, 512} and ordinary or nontemporal loads and
-    stores; DIRECT with tile_n 1, unroll 8  (<= 19)
+    {1, 2, 4}, block in {256, 512} and ordinary or nontemporal loads;
+    DIRECT with tile_n 1, unroll 8  (<= 19)
   * BF16 dtypes: columns per lane in {1, 4} (4 when it divides the extent),
     block in {256, 512}  (<= 4)
 Candidates that the specializer rejects for a shape (register or LDS limits)
@@ -67,7 +67,7 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
                 out.append(dict(variant=sj.SJ_VAR_STAGED, tile_n=tn, tile_k=tk, block=256))
         for rt in (1, 2, 4):
             for block in (256, 512):
-                for fl in (sj.SJ_FLAG_CACHED, sj.SJ_FLAG_NONTEMPORAL):
+                for fl in (0, sj.SJ_FLAG_LOADS_NONTEMPORAL):
                     out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, flags=fl))
         out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=1, unroll=8, block=256))
     return out

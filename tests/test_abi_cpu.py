@@ -263,20 +263,29 @@ def test_bgemm_prefetch_form(P):
 
 
 def test_load_store_policy_flags(P):
-    """The streamed-operand policy: the structure's default, or an explicit
-    flag, which is part of the key; the two flags exclude each other."""
-    base = dict(Z=4096, G=8, D=48, NM=16, flags=P.SJ_FLAG_COMPILE_ONLY)
-    assert "#define SJ_NT 0" in P.sj_emit_source(P.SJ_LTIMES, layout="ZGD", variant=P.SJ_VAR_MFMA, **base)
-    assert "#define SJ_NT 1" in P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", **base)
-    src = P.sj_emit_source(P.SJ_LTIMES, layout="ZGD", variant=P.SJ_VAR_MFMA,
-                           **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_NONTEMPORAL))
-    assert "#define SJ_NT 1" in src
-    src = P.sj_emit_source(P.SJ_LTIMES, layout="DGZ", **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED))
-    assert "#define SJ_NT 0" in src
-    h0 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", **base)
-    h1 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED))
+    """The streamed-operand policy: the structure's default, or explicit
+    flags for loads and for stores, which are part of the key; the two flags
+    of a pair exclude each other."""
+    base = dict(Z=4096, G=8, D=48, NM=16)
+    co = P.SJ_FLAG_COMPILE_ONLY
+
+    def src(layout, flags=0, **kw):
+        return P.sj_emit_source(P.SJ_LTIMES, layout=layout, flags=co | flags, **dict(base, **kw))
+    rows = src("ZGD", variant=P.SJ_VAR_MFMA)
+    assert "#define SJ_NT_LOAD 0" in rows and "#define SJ_NT_STORE 1" in rows
+    cols = src("DGZ")
+    assert "#define SJ_NT_LOAD 1" in cols and "#define SJ_NT_STORE 1" in cols
+    lplus = P.sj_emit_source(P.SJ_LPLUSTIMES, layout="DGZ", flags=co, **base)
+    assert "#define SJ_NT_LOAD 0" in lplus and "#define SJ_NT_STORE 1" in lplus
+    mixed = src("DGZ", P.SJ_FLAG_STORES_CACHED)
+    assert "#define SJ_NT_LOAD 1" in mixed and "#define SJ_NT_STORE 0" in mixed
+    mixed = src("ZGD", P.SJ_FLAG_LOADS_NONTEMPORAL | P.SJ_FLAG_STORES_CACHED, variant=P.SJ_VAR_MFMA)
+    assert "#define SJ_NT_LOAD 1" in mixed and "#define SJ_NT_STORE 0" in mixed
+    h0 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co, **base)
+    h1 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co | P.SJ_FLAG_STORES_CACHED, **base)
     assert h0 != h1
-    with pytest.raises(P.SJError) as e:
-        P.sj_specialize(P.SJ_LTIMES, layout="DGZ",
-                        **dict(base, flags=P.SJ_FLAG_COMPILE_ONLY | P.SJ_FLAG_CACHED | P.SJ_FLAG_NONTEMPORAL))
-    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    for bad in (P.SJ_FLAG_LOADS_CACHED | P.SJ_FLAG_LOADS_NONTEMPORAL,
+                P.SJ_FLAG_STORES_CACHED | P.SJ_FLAG_STORES_NONTEMPORAL):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co | bad, **base)
+        assert e.value.status == P.SJ_ERR_INVALID_ARG
