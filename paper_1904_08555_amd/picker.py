@@ -1,9 +1,10 @@
 """Learned specialization picker (cost model) and its evaluation.
 
 The exhaustive autotuner compiles and times every candidate specialization
-C(s) of a shape s; the picker instead predicts each candidate's run time with
-a small MLP and compiles only the predicted best.  The network (features ->
-64 -> 64 -> 1, ReLU, FP32) is trained on GPU with the library's own kernels
+C(s) of a shape s; the picker instead predicts each candidate's run time
+relative to the shape's other candidates and compiles only the predicted best.
+Five networks (features -> 64 -> 64 -> 1, ReLU, FP32, different seeds) are
+averaged; each is trained on GPU with the library's own kernels
 (SJ_MLP_BWD for the loss gradient, SJ_ADAM for the update, SJ_MLP_FWD for
 prediction), on timings the library itself gathers with sj_time_run.  This is
 the profile-guided, adaptive specialization named as future work in ClangJIT
@@ -17,7 +18,7 @@ NM ~ U{4, 9, 16, 36, 64}, dtype ~ U{FP64, BF16x3}.  Candidates:
   FP64, D innermost (GZD, ZGD): FP64-MFMA rows, tile_n in {1, 2, 4};
   BF16x3 (column layouts only): columns per lane in {1, 4} (4 when it
       divides the contiguous extent), block 256.
-The cost of a candidate is the median of 3 timed launches of one LTimes (after
+The cost of a candidate is the median of 5 timed launches of one LTimes (after
 one warm-up), with L2 and the last-level cache flushed first when the working
 set is under 512 MB.  Regret of a pick: t(pick) / min_c t(c) - 1.
 """
@@ -33,7 +34,7 @@ from . import sj
 
 LAYOUTS = sj.LAYOUTS
 COLUMN_LAYOUTS = ("DGZ", "DZG", "GDZ", "ZDG")
-NFEAT = 24
+NFEAT = 30
 WIDTH = 64
 
 
@@ -80,30 +81,76 @@ def default_candidate(shape: dict) -> dict:
     return dict(layout="DGZ")
 
 
+def resolved(shape: dict, cand: dict) -> dict:
+    """The tile parameters the specializer resolves for a candidate (its
+    defaults restated for LTimes), so that features see what will run."""
+    Z, G, NM = shape["Z"], shape["G"], shape["NM"]
+    lay = cand.get("layout", "DGZ")
+    I = contiguous_extent(lay, Z, G)
+    B = G * Z // I
+    f64 = shape["dtype"] == sj.SJ_F64
+    var = cand.get("variant", 0) or (sj.SJ_VAR_MFMA if (not f64 or I == 1) else sj.SJ_VAR_DIRECT)
+    ob = (NM + 15) // 16
+    r = dict(I=I, B=B, variant=var, block=cand.get("block", 0) or 256, order=cand.get("order", 0))
+    far = I * 8 >= (1 << 20)
+    if var == sj.SJ_VAR_DIRECT:
+        r["tile"] = cand.get("tile_n", 0) or (2 if I % 2 == 0 and NM <= 16 else 1)
+        r["unroll"] = cand.get("unroll", 0) or 8
+        r["order"] = r["order"] or (2 if far else 1)
+        r["width"], r["acc"] = 1, NM * r["tile"]
+    elif not f64:
+        r["tile"] = cand.get("tile_n", 0) or (4 if I % 4 == 0 else 1)
+        r["unroll"] = 1
+        r["order"] = 1
+        r["width"], r["acc"] = 32 * r["tile"], ((NM + 31) // 32) * 16 * r["tile"]
+    elif I > 1:
+        t = cand.get("tile_n", 0)
+        if not t:
+            t = 1
+            for c in (4, 2):
+                if I % c == 0 and ob * 4 * c <= 32:
+                    t = c
+                    break
+        r["tile"] = t
+        r["unroll"] = cand.get("unroll", 0) or max(1, min(16 // t, 32 // (ob * t)))
+        r["order"] = r["order"] or (2 if far else 1)
+        r["width"], r["acc"] = 16 * t, ob * 4 * t
+    else:
+        rt = cand.get("tile_n", 0) or (2 if 8 * ob <= 96 else 1)
+        r["tile"], r["unroll"], r["order"] = rt, 1, 1
+        r["width"], r["acc"] = 1, rt * ob * 4
+    return r
+
+
 def features(shape: dict, cand: dict) -> np.ndarray:
     """Raw (unnormalized) feature vector of NFEAT floats."""
     f = np.zeros(NFEAT, dtype=np.float64)
     Z, G, D, NM = shape["Z"], shape["G"], shape["D"], shape["NM"]
     lay = cand.get("layout", "DGZ")
     esz = 8 if shape["dtype"] == sj.SJ_F64 else 4
+    r = resolved(shape, cand)
+    I, B, var = r["I"], r["B"], r["variant"]
     f[0:4] = [math.log2(Z), math.log2(G), math.log2(D), math.log2(NM)]
     f[4] = 1.0 if shape["dtype"] == sj.SJ_F64 else 0.0
     f[5] = 1.0 - f[4]
     f[6 + LAYOUTS.index(lay)] = 1.0
-    var = cand.get("variant", 0)
-    if var == 0:
-        var = sj.SJ_VAR_MFMA if (shape["dtype"] != sj.SJ_F64 or lay not in COLUMN_LAYOUTS) else sj.SJ_VAR_DIRECT
     f[12 + (var - 1)] = 1.0
-    f[15] = math.log2(max(1, cand.get("tile_n", 0) or 1))
-    f[16] = cand.get("unroll", 8) / 16.0
-    f[17] = cand.get("block", 256) / 512.0
-    f[18] = 1.0 if cand.get("order", 0) == 2 else 0.0
-    ext = contiguous_extent(lay, Z, G)
-    f[19] = math.log2(ext * esz)                          # contiguous run in bytes
+    f[15] = math.log2(r["tile"])
+    f[16] = r["unroll"] / 16.0
+    f[17] = r["block"] / 512.0
+    f[18] = 1.0 if r["order"] == 2 else 0.0
+    f[19] = math.log2(I * esz)                             # contiguous run in bytes
     f[20] = math.log2((D + NM) * G * Z * esz)             # algorithmic bytes
     f[21] = math.log2(2.0 * D * NM * G * Z)               # flops
-    f[22] = math.log2(max(1, ext) * esz * 1.0) if lay in ("DGZ", "DZG") else math.log2(Z * esz)  # row stride proxy
+    f[22] = math.log2(I * esz) if lay in ("DGZ", "DZG") else math.log2(Z * esz)  # row stride proxy
     f[23] = 1.0
+    w = r["width"]
+    f[24] = I / (((I + w - 1) // w) * w)                  # share of lanes with a real column
+    f[25] = math.log2(B)
+    f[26] = math.log2(r["acc"])                            # accumulators per lane
+    f[27] = 1.0 if (var == sj.SJ_VAR_MFMA and shape["dtype"] == sj.SJ_F64 and I > 1) else 0.0
+    f[28] = 1.0 if I == 1 else 0.0
+    f[29] = math.log2(I)
     return f
 
 
@@ -146,7 +193,7 @@ def spec_of(shape: dict, cand: dict) -> dict:
     return spec
 
 
-def time_items(farm, bufs: Buffers, items, log=None, reps: int = 3):
+def time_items(farm, bufs: Buffers, items, log=None, reps: int = 5):
     """items: [(shape, cand)] -> [median ms or None] (None when the specializer
     rejects the candidate)."""
     t0 = time.time()
@@ -242,54 +289,80 @@ class MLP:
 
 
 class Picker:
-    """Standardized features and log-time targets around an MLP."""
+    """An ensemble of MLPs over standardized features.  The target of a training
+    timing is its log-time relative to the mean log-time of the candidates
+    timed for the same shape: the pick only compares candidates of one shape,
+    so the network is not asked to learn the (much larger) differences between
+    shapes.  Predictions are relative log-times; the pick is their argmin."""
 
-    def __init__(self, seed: int = 0):
-        self.mlp = MLP(seed=seed)
+    def __init__(self, seed: int = 0, members: int = 5):
+        self.mlps = [MLP(seed=seed + 101 * k) for k in range(members)]
         self.mu = np.zeros(NFEAT)
         self.sd = np.ones(NFEAT)
-        self.tmu = 0.0
         self.tsd = 1.0
 
     def _norm(self, F):
         return (F - self.mu) / self.sd
 
-    def fit(self, shapes_cands, times_ms, epochs=300, log=None):
-        F = np.stack([features(s, c) for s, c in shapes_cands])
+    @staticmethod
+    def relative_targets(shapes_cands, times_ms):
+        """log t minus the mean log t of the same shape's timed candidates; None
+        for shapes with fewer than two timed candidates."""
+        groups = {}
+        for i, (s, _) in enumerate(shapes_cands):
+            groups.setdefault(json.dumps(s, sort_keys=True), []).append(i)
+        out = [None] * len(times_ms)
+        for idx in groups.values():
+            if len(idx) < 2:
+                continue
+            lt = np.log(np.array([times_ms[i] for i in idx], dtype=np.float64))
+            for i, v in zip(idx, lt - lt.mean()):
+                out[i] = float(v)
+        return out
+
+    def fit(self, shapes_cands, times_ms, epochs=200, batch=64, log=None):
+        rel = self.relative_targets(shapes_cands, times_ms)
+        keep = [i for i, r in enumerate(rel) if r is not None]
+        F = np.stack([features(*shapes_cands[i]) for i in keep])
+        t = np.array([rel[i] for i in keep])
         self.mu = F.mean(axis=0)
         self.sd = F.std(axis=0)
         self.sd[self.sd < 1e-9] = 1.0
         self.mu[NFEAT - 1] = 0.0     # keep the constant feature
-        t = np.log(np.asarray(times_ms, dtype=np.float64))
-        self.tmu, self.tsd = float(t.mean()), float(t.std() or 1.0)
-        return self.mlp.fit(self._norm(F), (t - self.tmu) / self.tsd, epochs=epochs, log=log)
+        self.tsd = float(t.std() or 1.0)
+        losses = []
+        for k, m in enumerate(self.mlps):
+            losses = m.fit(self._norm(F), t / self.tsd, epochs=epochs, batch=batch, seed=k, log=log if k == 0 else None)
+        return losses
 
-    def predict_ms(self, shape, cands) -> np.ndarray:
-        F = np.stack([features(shape, c) for c in cands])
-        return np.exp(self.mlp.predict(self._norm(F)) * self.tsd + self.tmu)
+    def predict_rel(self, shape, cands) -> np.ndarray:
+        F = self._norm(np.stack([features(shape, c) for c in cands]))
+        return np.mean([m.predict(F) for m in self.mlps], axis=0) * self.tsd
 
     def pick(self, shape, cands=None):
         cands = candidates(shape) if cands is None else cands
-        pred = self.predict_ms(shape, cands)
+        pred = self.predict_rel(shape, cands)
         i = int(np.argmin(pred))          # ties: lowest candidate index
         return cands[i], pred
 
     def save(self, path):
         with open(path, "w") as f:
-            json.dump(dict(theta=self.mlp.theta.cpu().numpy().tolist(), mu=self.mu.tolist(), sd=self.sd.tolist(),
-                           tmu=self.tmu, tsd=self.tsd, nfeat=NFEAT, width=WIDTH), f)
+            json.dump(dict(thetas=[m.theta.cpu().numpy().tolist() for m in self.mlps], mu=self.mu.tolist(),
+                           sd=self.sd.tolist(), tsd=self.tsd, nfeat=NFEAT, width=WIDTH), f)
 
     def load(self, path):
         import torch
         with open(path) as f:
             d = json.load(f)
-        self.mlp.theta = torch.tensor(d["theta"], dtype=torch.float32, device="cuda")
+        self.mlps = [MLP() for _ in d["thetas"]]
+        for m, th in zip(self.mlps, d["thetas"]):
+            m.theta = torch.tensor(th, dtype=torch.float32, device="cuda")
         self.mu, self.sd = np.array(d["mu"]), np.array(d["sd"])
-        self.tmu, self.tsd = d["tmu"], d["tsd"]
+        self.tsd = d["tsd"]
 
 
 def run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=8, epochs=300, log=print,
-                   max_k=64):
+                   max_k=64, dump=None):
     """Collect training timings, train the picker, evaluate regret on held-out
     shapes against the exhaustive tuner's best, and the gain over the
     untuned default.  Returns a result dict."""
@@ -338,6 +411,7 @@ def run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=
         ev_times = time_items(farm, bufs, ev_items, log=log)
         res["eval_collect_s"] = round(time.time() - t0, 1)
     regrets, regrets2, gains, picks_ok = [], [], [], 0
+    per_shape_rows = []
     for i, s in enumerate(eval_shapes):
         cs = [(c, t) for (ss, c), o, t in zip(ev_items, owner, ev_times) if o == i and t is not None]
         dflt = [t for (ss, c), o, t in zip(ev_items, owner, ev_times) if o == -1 - i and t is not None]
@@ -352,8 +426,13 @@ def run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=
         # top-2: compile and time the two best-predicted candidates, keep the faster
         two = np.argsort(pred, kind="stable")[:2]
         regrets2.append(min(t_of[json.dumps(cands[int(j)], sort_keys=True)] for j in two) / best - 1.0)
+        per_shape_rows.append(dict(shape=s, times=[(c, t) for c, t in cs], pred=[float(x) for x in pred],
+                                   pick=pick, default_ms=dflt[0]))
         gains.append(dflt[0] / t_pick)
         picks_ok += 1
+    if dump:
+        with open(dump, "w") as f:
+            json.dump(dict(train=[(sc[0], sc[1], t) for sc, t in pairs], eval=per_shape_rows), f)
     r = np.array(regrets)
     g = np.array(gains)
     res.update(dict(

@@ -399,3 +399,23 @@ def test_mfma64_cols_full_size_sampled(P, orc, layout):
     assert componentwise_err(out_log[:, g, z], ref2, scale2) <= TOL_F64
     del psi_d, phi_d, out_d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("layout,variant", [("DGZ", 1), ("DGZ", 3), ("GDZ", 1), ("ZGD", 3), ("ZGD", 2)],
+                         ids=["direct-dgz", "cols-dgz", "direct-gdz", "rows-zgd", "staged-zgd"])
+def test_policy_flags_bitwise_identical(P, orc, layout, variant):
+    """The load/store policy changes only the memory instructions: every
+    combination gives the default's output bit for bit (and the default
+    meets the oracle bar)."""
+    Z, G, D, NM = 300, 3, 48, 16
+    L, Lp, psi, phi_in = contraction_inputs(12, layout, Z, G, D, NM)
+    ref = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), variant=variant))
+    assert componentwise_err(ref, orc.ltimes(layout, Z, G, D, NM, L, psi),
+                             orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)) <= TOL_F64
+    ref2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), variant=variant))
+    for lf in (P.SJ_FLAG_LOADS_CACHED, P.SJ_FLAG_LOADS_NONTEMPORAL):
+        for sf in (P.SJ_FLAG_STORES_CACHED, P.SJ_FLAG_STORES_NONTEMPORAL):
+            got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), variant=variant, flags=lf | sf))
+            assert np.array_equal(got, ref), (lf, sf)
+            got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), variant=variant, flags=lf | sf))
+            assert np.array_equal(got2, ref2), (lf, sf)
