@@ -252,9 +252,16 @@ class MLP:
                                                width=self.H)
         return self._bwd[rows]
 
+    def _check_rows(self, X):
+        # the kernels read rows of exactly self.F floats: a wider or narrower
+        # array would be read past its end or misaligned
+        if X.ndim != 2 or X.shape[1] != self.F:
+            raise ValueError(f"feature rows must have {self.F} columns, got shape {X.shape}")
+
     def predict(self, X: np.ndarray) -> np.ndarray:
         import torch
         X = np.ascontiguousarray(X, dtype=np.float32)
+        self._check_rows(X)
         x_d = torch.from_numpy(X).cuda()
         y_d = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
         sj.sj_run(self._h_fwd(X.shape[0]), [self.theta, x_d, y_d])
@@ -265,7 +272,10 @@ class MLP:
         import torch
         X = np.ascontiguousarray(X, dtype=np.float32)
         y = np.ascontiguousarray(y, dtype=np.float32)
+        self._check_rows(X)
         n = X.shape[0]
+        if y.shape != (n,) or n < batch:
+            raise ValueError(f"need one target per row and at least {batch} rows, got X {X.shape}, y {y.shape}")
         nb = n // batch
         rng = np.random.default_rng(seed)
         grad = torch.empty(self.P, dtype=torch.float32, device="cuda")

@@ -72,7 +72,9 @@ def test_mlp_training_reduces_loss(P):
     rng = np.random.default_rng(0)
     X = rng.standard_normal((1024, 24)).astype(np.float32)
     y = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
-    mlp = MLP(seed=0)
+    mlp = MLP(nfeat=24, seed=0)
+    with pytest.raises(ValueError):
+        MLP(seed=0, nfeat=30).fit(X, y, epochs=1)    # rows of the wrong width are refused on the host
     losses = mlp.fit(X, y, epochs=60, batch=128, lr=3e-3)
     assert losses[-1] < 0.25 * losses[0]
     pred = mlp.predict(X)
