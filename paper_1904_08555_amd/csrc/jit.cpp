@@ -99,7 +99,37 @@ static void layout_view(int layout, int64_t Z, int64_t G, int64_t *B, int64_t *I
 
 static bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 
+static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const char *arch, SpecKey *out);
+
+// SJ_VAR_AUTO on an FP64 contraction: the preferred structure for the layout,
+// and when that one declines the shape (SJ_ERR_UNSUPPORTED: register, LDS or
+// size limits) the next structure that accepts it, so that every valid shape
+// has a default.  D innermost: MFMA rows, STAGED, DIRECT; a column axis
+// innermost: DIRECT, MFMA columns.
 sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, SpecKey *out)
+{
+    if (!s || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output");
+    if (s->struct_size != sizeof(sj_spec))
+        return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size does not match this library's sj_spec");
+    if (!((k == SJ_LTIMES || k == SJ_LPLUSTIMES) && s->variant == SJ_VAR_AUTO && s->dtype == SJ_F64))
+        return make_key_one(k, s, device, arch, out);
+    int64_t B = 0, I = 0;
+    if (s->layout >= SJ_DGZ && s->layout <= SJ_ZGD && s->Z >= 1 && s->G >= 1) layout_view(s->layout, s->Z, s->G, &B, &I);
+    static const int kRows[3] = {SJ_VAR_MFMA, SJ_VAR_STAGED, SJ_VAR_DIRECT};
+    static const int kCols[2] = {SJ_VAR_DIRECT, SJ_VAR_MFMA};
+    const int *order = (I == 1) ? kRows : kCols;
+    const int n = (I == 1) ? 3 : 2;
+    sj_status st = SJ_ERR_UNSUPPORTED;
+    for (int i = 0; i < n; ++i) {
+        sj_spec t = *s;
+        t.variant = order[i];
+        st = make_key_one(k, &t, device, arch, out);
+        if (st != SJ_ERR_UNSUPPORTED) return st;
+    }
+    return st;
+}
+
+static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const char *arch, SpecKey *out)
 {
     if (!s || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output");
     if (s->struct_size != sizeof(sj_spec))
@@ -190,6 +220,12 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
             key.tile_k = (int32_t)std::min<int64_t>(key.tile_k, s->D);
             const int64_t rpt = key.tile_n / key.block;
             if (s->NM * rpt > 128) return fail(SJ_ERR_UNSUPPORTED, "NM * rows per thread > 128 FP64 values per thread");
+            // STAGED unrolls every chunk of the reduction (or of the outputs) at compile time:
+            // bound that work, or hiprtc's time grows without limit (D = 4096 took over half an
+            // hour, D = 512 with NM = 16 eleven seconds)
+            const int64_t nchunk = (s->D + key.tile_k - 1) / key.tile_k;
+            if (nchunk > 16 || s->D * s->NM * rpt > 4096)
+                return fail(SJ_ERR_UNSUPPORTED, "STAGED unrolls at most 16 chunks and 4096 products per row set");
             const int64_t lds = (int64_t)key.tile_n * std::max<int64_t>(key.tile_k + 1, s->NM + 1) * 8;
             if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "STAGED tile exceeds 160 KiB of LDS");
             key.unroll = 0;

@@ -419,3 +419,52 @@ def test_policy_flags_bitwise_identical(P, orc, layout, variant):
             assert np.array_equal(got, ref), (lf, sf)
             got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), variant=variant, flags=lf | sf))
             assert np.array_equal(got2, ref2), (lf, sf)
+
+
+@pytest.mark.parametrize("layout,spec", [
+    ("DGZ", dict(variant=1)), ("ZDG", dict(variant=1, tile_n=1)), ("DGZ", dict(variant=3)), ("GDZ", dict(variant=3)),
+    ("ZGD", dict(variant=3)), ("GZD", dict(variant=2)), ("DZG", dict(variant=1, order=2, tile_n=2, unroll=4))],
+    ids=["direct-dgz", "direct-zdg", "cols-dgz", "cols-gdz", "rows-zgd", "staged-gzd", "direct-dzg-rot"])
+def test_index64_forced_small(P, orc, layout, spec):
+    """64-bit indexing (chosen automatically for arrays of 2^31 elements and
+    more) forced at a small shape for every structure: the same results."""
+    Z, G, D, NM = 300, 3, 48, 16
+    L, Lp, psi, phi_in = contraction_inputs(13, layout, Z, G, D, NM)
+    spec = dict(spec, flags=P.SJ_FLAG_INDEX64)
+    got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), **spec))
+    assert componentwise_err(got, orc.ltimes(layout, Z, G, D, NM, L, psi),
+                             orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)) <= TOL_F64
+    got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), **spec))
+    assert componentwise_err(got2, orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in),
+                             orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)) <= TOL_F64
+    h = P.sj_specialize(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, **spec)
+    assert "typedef long long sj_index_t" in P.sj_emit_source(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM,
+                                                               **spec)
+    assert P.sj_handle_info(h)["scratch_bytes"] == 0
+
+
+@pytest.mark.parametrize("shape", [(64, 2, 4096, 2), (33, 3, 4096, 5), (40, 2, 8, 128), (7, 5, 3, 128)],
+                         ids=["D4096NM2", "D4096NM5", "D8NM128", "D3NM128"])
+@pytest.mark.parametrize("layout", ["DGZ", "ZDG", "GZD"])
+def test_edge_sizes(P, orc, layout, shape):
+    """The largest reduction length (D = 4096) and the largest moment count a
+    column keeps in registers (NM = 128), through the default structures and
+    the generic kernels; a structure that declines a shape says so."""
+    Z, G, D, NM = shape
+    L, Lp, psi, phi_in = contraction_inputs(14, layout, Z, G, D, NM)
+    ref = orc.ltimes(layout, Z, G, D, NM, L, psi)
+    scale = orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)
+    ref2 = orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in)
+    scale2 = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)
+    for generic in (False, True):
+        print(f"case edge layout={layout} shape={shape} generic={generic}", flush=True)
+        try:
+            got = host(run_ltimes(P, layout, Z, G, D, NM, dev(L), dev(psi), generic))
+            assert componentwise_err(got, ref, scale) <= TOL_F64
+        except P.SJError as e:
+            assert not generic and e.status == P.SJ_ERR_UNSUPPORTED, e
+        try:
+            got2 = host(run_lplus(P, layout, Z, G, D, NM, dev(Lp), dev(phi_in), generic))
+            assert componentwise_err(got2, ref2, scale2) <= TOL_F64
+        except P.SJError as e:
+            assert not generic and e.status == P.SJ_ERR_UNSUPPORTED, e
