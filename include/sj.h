@@ -113,6 +113,9 @@ typedef enum sj_variant {
 #define SJ_FLAG_LOADS_NONTEMPORAL 0x8u  /* LTimes / LPlusTimes: nontemporal loads of the streamed input */
 #define SJ_FLAG_STORES_CACHED     0x10u /* LTimes / LPlusTimes: ordinary stores of the output */
 #define SJ_FLAG_STORES_NONTEMPORAL 0x20u /* LTimes / LPlusTimes: nontemporal stores of the output */
+#define SJ_FLAG_ACCUMULATE        0x40u /* LTimes / LPlusTimes: add the result to the output's current values
+                                           (phi += L psi, psi' += L+ phi: several direction sets summed into one
+                                           output) instead of overwriting; the output is then also read */
 /* Without a loads flag (stores flag) the default measured on MI355X applies:
  * nontemporal stores for every streamed output; nontemporal loads for LTimes'
  * column kernels, ordinary loads for LPlusTimes and for the FP64 MFMA row

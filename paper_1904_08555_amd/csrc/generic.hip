@@ -132,6 +132,7 @@ extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *cons
     hipStream_t st = (hipStream_t)stream;
     if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
         if (spec->dtype != SJ_F64) return fail(SJ_ERR_UNSUPPORTED, "generic kernels are FP64 only");
+        if (spec->flags & SJ_FLAG_ACCUMULATE) return fail(SJ_ERR_UNSUPPORTED, "generic kernels overwrite their output");
         if (spec->layout < SJ_DGZ || spec->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
         const long long Z = spec->Z, G = spec->G, D = spec->D, NM = spec->NM;
         if (Z < 1 || G < 1 || D < 1 || NM < 1 || Z > 2147483647LL || G > 2147483647LL || D > 2147483647LL ||

@@ -142,7 +142,10 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     key.lib_version = SJ_VERSION;
     std::snprintf(key.arch, sizeof key.arch, "%s", arch ? arch : "");
     key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE | SJ_FLAG_LOADS_CACHED |
-                            SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED | SJ_FLAG_STORES_NONTEMPORAL);
+                            SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED | SJ_FLAG_STORES_NONTEMPORAL |
+                            SJ_FLAG_ACCUMULATE);
+    if ((s->flags & SJ_FLAG_ACCUMULATE) && k != SJ_LTIMES && k != SJ_LPLUSTIMES)
+        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_ACCUMULATE applies to LTimes and LPlusTimes");
     if ((s->flags & SJ_FLAG_LOADS_CACHED) && (s->flags & SJ_FLAG_LOADS_NONTEMPORAL))
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_LOADS_CACHED and SJ_FLAG_LOADS_NONTEMPORAL exclude each other");
     if ((s->flags & SJ_FLAG_STORES_CACHED) && (s->flags & SJ_FLAG_STORES_NONTEMPORAL))
@@ -399,9 +402,14 @@ static const char *kCommonPrologue =
     "#define SJ_LOAD(p) (*(p))\n"
     "#endif\n"
     "#if SJ_NT_STORE\n"
-    "#define SJ_STORE(v, p) __builtin_nontemporal_store((v), (p))\n"
+    "#define SJ_STORE_RAW(v, p) __builtin_nontemporal_store((v), (p))\n"
     "#else\n"
-    "#define SJ_STORE(v, p) (*(p) = (v))\n"
+    "#define SJ_STORE_RAW(v, p) (*(p) = (v))\n"
+    "#endif\n"
+    "#if SJ_ACCUM\n"
+    "#define SJ_STORE(v, p) SJ_STORE_RAW((v) + *(p), (p))\n"
+    "#else\n"
+    "#define SJ_STORE(v, p) SJ_STORE_RAW((v), (p))\n"
     "#endif\n";
 
 // The templates name their kernel through this macro.
@@ -434,7 +442,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
         if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
         if (k.flags & SJ_FLAG_STORES_NONTEMPORAL) nts = 1;
-        o << "#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n";
+        o << "#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM "
+          << ((k.flags & SJ_FLAG_ACCUMULATE) ? 1 : 0) << "\n";
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
               << k.full_unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
@@ -465,7 +474,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
     }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {
         o << "#define SJ_R " << k.rows << "\n#define SJ_F " << (k.inputs ? k.inputs : 1) << "\n#define SJ_H "
-          << (k.width ? k.width : 1) << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n"
+          << (k.width ? k.width : 1) << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n#define SJ_ACCUM 0\n"
           << "#define SJ_WANT_FWD " << (k.kernel == SJ_MLP_FWD) << "\n#define SJ_WANT_BWD " << (k.kernel == SJ_MLP_BWD)
           << "\n#define SJ_WANT_ADAM " << (k.kernel == SJ_ADAM) << "\n";
         body = kTpl_mlp;
@@ -485,7 +494,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
                 o << " case " << n << ": it = sj_bgemm_class<" << n << ">(Ms, Ls, it, nitems, As, Bs); break;";
-        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n";
+        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n#define SJ_ACCUM 0\n";
         bgemm_common = kTpl_bgemm_common;
         body = wave_form ? kTpl_bgemm_wave : kTpl_bgemm;
         *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";

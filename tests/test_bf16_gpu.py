@@ -171,3 +171,22 @@ def test_fp64_large_config_sampled(P, orc):
         torch.cuda.empty_cache()
     del psi_d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cols_per_lane", [1, 4])
+def test_bf16_accumulate_exact(P, orc, cols_per_lane):
+    """SJ_FLAG_ACCUMULATE in BF16: small-integer inputs make every product and
+    partial sum exact in FP32, so out0 + 2 L psi comes out bit for bit."""
+    Z, G, D, NM = 64, 4, 32, 8
+    rng = np.random.default_rng(5)
+    Li = rng.integers(-4, 5, (NM, D)).astype(float)
+    pi = rng.integers(0, 8, D * G * Z).astype(float)
+    out0 = rng.integers(-50, 50, NM * G * Z).astype(np.float32)
+    ref = orc.ltimes("DGZ", Z, G, D, NM, Li, pi)
+    for dt in (P.SJ_BF16, P.SJ_BF16X3):
+        phi_d = dev(out0.copy())
+        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt, tile_n=cols_per_lane,
+                            flags=P.SJ_FLAG_ACCUMULATE)
+        for _ in range(2):
+            P.sj_run(h, [dev(Li), dev(pi.astype(np.float32)), phi_d])
+        assert np.array_equal(host(phi_d).astype(np.float64), out0.astype(np.float64) + 2 * ref)

@@ -468,3 +468,43 @@ def test_edge_sizes(P, orc, layout, shape):
             assert componentwise_err(got2, ref2, scale2) <= TOL_F64
         except P.SJError as e:
             assert not generic and e.status == P.SJ_ERR_UNSUPPORTED, e
+
+
+@pytest.mark.parametrize("layout,spec", [
+    ("DGZ", dict(variant=1)), ("DGZ", dict(variant=3)), ("GDZ", dict(variant=1)), ("ZDG", dict(variant=3)),
+    ("ZGD", dict(variant=3)), ("GZD", dict(variant=2)), ("DZG", dict(variant=1, order=2, tile_n=2, unroll=4))],
+    ids=["direct-dgz", "cols-dgz", "direct-gdz", "cols-zdg", "rows-zgd", "staged-gzd", "direct-dzg"])
+def test_accumulate(P, orc, layout, spec):
+    """SJ_FLAG_ACCUMULATE: out += result on every structure.  Bar: the FP64
+    componentwise bound widened by the one extra addition,
+    |got - (out0 + oracle)| <= 1e-12 (sum|L||psi| + |out0|)."""
+    Z, G, D, NM = 300, 3, 48, 16
+    L, Lp, psi, phi_in = contraction_inputs(15, layout, Z, G, D, NM)
+    init = gen.sym(15, gen.ARR_PHI + 10, np.arange(max(NM, D) * G * Z, dtype=np.uint64))
+    spec = dict(spec)
+    spec["flags"] = spec.get("flags", 0) | P.SJ_FLAG_ACCUMULATE
+    out0 = init[:NM * G * Z].copy()
+    phi_d = dev(out0)
+    h = P.sj_specialize(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, **spec)
+    P.sj_run(h, [dev(L), dev(psi), phi_d])
+    P.sj_run(h, [dev(L), dev(psi), phi_d])       # two direction sets summed
+    ref = orc.ltimes(layout, Z, G, D, NM, L, psi)
+    scale = orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)
+    assert componentwise_err(host(phi_d), out0 + 2 * ref, 2 * scale + np.abs(out0)) <= TOL_F64
+    out1 = init[:D * G * Z].copy()
+    o_d = dev(out1)
+    h2 = P.sj_specialize(P.SJ_LPLUSTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, **spec)
+    P.sj_run(h2, [dev(Lp), dev(phi_in), o_d])
+    ref2 = orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in)
+    scale2 = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)
+    assert componentwise_err(host(o_d), out1 + ref2, scale2 + np.abs(out1)) <= TOL_F64
+
+
+def test_accumulate_refused_where_unsupported(P):
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_BGEMM, flags=P.SJ_FLAG_ACCUMULATE)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    x = torch.zeros(64, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.SJError) as e:
+        P.sj_generic_run(P.SJ_LTIMES, [x, x, x], layout="DGZ", Z=2, G=2, D=2, NM=2, flags=P.SJ_FLAG_ACCUMULATE)
+    assert e.value.status == P.SJ_ERR_UNSUPPORTED
