@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "gpurun_out/tuned_moments.json) instead of tuning")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy"),
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -110,6 +110,8 @@ def main():
         return bench_picker(a)
     if a.workload == "copy":
         return bench_copy(a)
+    if a.workload == "fused":
+        return bench_fused(a)
     return bench_moments(a)
 
 
@@ -575,6 +577,69 @@ def bench_bf16(a):
         "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": best["frac"], "traffic": None, "kernel": best["kernel"], "bytes_per_launch": b32},
         "modes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_fused(a):
+    """LTimes then LPlusTimes per nesting as one fused pass (phi kept in
+    registers; written out too, or not) against the two separate kernels, FP64,
+    Z=32768 G=32 D=96 NM=16, default specializations.  value = algorithmic
+    bytes of the fused step (with phi written) / its time."""
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+    from sj_inputs import device as gdev
+
+    Z, G, D, NM = a.Z, a.G, a.D, a.NM
+    layouts = [x for x in a.layouts.split(",") if x]
+    stream = torch.cuda.current_stream()
+    L_d = torch.empty(NM * D, dtype=torch.float64, device="cuda")
+    Lp_d = torch.empty(D * NM, dtype=torch.float64, device="cuda")
+    gdev.fill(L_d, 0, gen.ARR_L, gdev.DIST_SYM)
+    gdev.fill(Lp_d, 0, gen.ARR_LPLUS, gdev.DIST_SYM)
+    psi = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    phi = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
+    out = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    cols = G * Z
+    b_with = (2 * D + NM) * cols * 8 + 2 * NM * D * 8
+    b_without = 2 * D * cols * 8 + 2 * NM * D * 8
+    b_sep = 2 * algorithmic_bytes(Z, G, D, NM)
+    res = {}
+    tot_fused, tot_sep = 0.0, 0.0
+    for lay in layouts:
+        gdev.fill(psi, 0, gen.ARR_PSI, gdev.DIST_U01, LAYOUTS.index(lay), (D, G, Z))
+        hf = P.sj_specialize(P.SJ_LTIMES_LPLUS, layout=lay, Z=Z, G=G, D=D, NM=NM)
+        h1 = P.sj_specialize(P.SJ_LTIMES, layout=lay, Z=Z, G=G, D=D, NM=NM)
+        h2 = P.sj_specialize(P.SJ_LPLUSTIMES, layout=lay, Z=Z, G=G, D=D, NM=NM)
+
+        def sep():
+            P.sj_run(h1, [L_d, psi, phi])
+            P.sj_run(h2, [Lp_d, phi, out])
+        fused_with, _ = time_launches(lambda: P.sj_run(hf, [L_d, Lp_d, psi, out, phi]), a.steps, stream)
+        fused_without, _ = time_launches(lambda: P.sj_run(hf, [L_d, Lp_d, psi, out]), a.steps, stream)
+        sep_ms, _ = time_launches(sep, a.steps, stream)
+        tot_fused += fused_with
+        tot_sep += sep_ms
+        res[lay] = dict(fused_us=round(fused_with * 1e3, 1), fused_gbs=round(b_with / (fused_with * 1e-3) / 1e9, 1),
+                        fused_no_phi_us=round(fused_without * 1e3, 1),
+                        fused_no_phi_gbs=round(b_without / (fused_without * 1e-3) / 1e9, 1),
+                        separate_us=round(sep_ms * 1e3, 1), speedup=round(sep_ms / fused_with, 3),
+                        kernel=P.sj_handle_info(hf)["kernel_name"])
+    dom = max(res, key=lambda k: res[k]["fused_us"])
+    line = {
+        "metric": "fused LTimes+LPlusTimes GB/s (phi kept on chip) vs the two separate kernels",
+        "value": round(b_with * len(layouts) / (tot_fused * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": 0, "ms_per_step": round(tot_fused, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64, seed 0)",
+        "config": {"workload": f"psi -> phi -> psi' per nesting, FP64, Z={Z} G={G} D={D} NM={NM}", "layouts": layouts},
+        "roofline": {"bound": "hbm", "achieved": res[dom]["fused_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(res[dom]["fused_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": res[dom]["kernel"], "avg_us": res[dom]["fused_us"], "bytes_per_launch": b_with},
+        "separate_ms_per_step": round(tot_sep, 4), "speedup_vs_separate": round(tot_sep / tot_fused, 3),
+        "bytes": {"fused_with_phi": b_with, "fused_without_phi": b_without, "separate_pair": b_sep},
+        "per_layout": res,
     }
     print(json.dumps(line), flush=True)
 

@@ -77,7 +77,8 @@ typedef enum sj_kernel {
     SJ_BGEMM = 3,
     SJ_MLP_FWD = 4,
     SJ_MLP_BWD = 5,
-    SJ_ADAM = 6
+    SJ_ADAM = 6,
+    SJ_LTIMES_LPLUS = 7    /* LTimes then LPlusTimes on the same columns in one pass (phi stays on chip) */
 } sj_kernel;
 
 /* Storage order of a psi-like array's three axes, rightmost fastest.  phi uses
@@ -206,8 +207,12 @@ sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *
 /* Launch a specialization.  No cache lookup happens here.  Pointers by kernel:
  *   SJ_LTIMES:     {L [NM*D] f64, psi [D*G*Z] (f64, or f32 for BF16 dtypes), phi [NM*G*Z] (same type as psi)}
  *   SJ_LPLUSTIMES: {L+ [D*NM] f64, phi [NM*G*Z] f64, psi_out [D*G*Z] f64}
+ *   SJ_LTIMES_LPLUS: {L [NM*D], L+ [D*NM], psi [D*G*Z], psi_out [D*G*Z]} or the same with
+ *                  phi [NM*G*Z] appended when the moments are wanted too (all f64); psi_out =
+ *                  L+ (L psi) with the moments held in registers (DIRECT structure, FP64)
  *   SJ_MLP_FWD:    {theta f32, X [rows*inputs] f32, y [rows] f32}
- *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32}
+ *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32,
+ *                  workspace [rows*(4*width+2)] f32}
  *   SJ_ADAM:       use sj_run_adam.
  * Checks: handle runnable, nptrs, pointers non-null and 16-byte aligned
  * (SJ_ERR_ALIGN), no overlap between an input and an output byte range

@@ -475,6 +475,21 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
         if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
         return SJ_OK;
     }
+    if (k.kernel == SJ_LTIMES_LPLUS) {
+        // {L, L+, psi, psi_out} or {L, L+, psi, psi_out, phi_out}
+        const size_t cols = (size_t)k.G * (size_t)k.Z;
+        const size_t bytes[5] = {(size_t)k.NM * (size_t)k.D * 8, (size_t)k.NM * (size_t)k.D * 8,
+                                 (size_t)k.D * cols * 8, (size_t)k.D * cols * 8, (size_t)k.NM * cols * 8};
+        const int n = (nptrs == 4) ? 4 : 5;
+        sj_status s = check_ptrs(ptrs, nptrs, n, bytes, 3);
+        if (s != SJ_OK) return s;
+        void *a0 = ptrs[0], *a1 = ptrs[1], *a2 = ptrs[2], *a3 = ptrs[3], *a4 = (n == 5) ? ptrs[4] : nullptr;
+        void *args[] = {&a0, &a1, &a2, &a3, &a4};
+        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0,
+                                             (hipStream_t)stream, args, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD) {
         const size_t R = (size_t)k.rows, F = (size_t)k.inputs, H = (size_t)k.width;
         const size_t P = (size_t)mlp_nparams(k.inputs, k.width);

@@ -146,12 +146,18 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
                             SJ_FLAG_ACCUMULATE);
     if ((s->flags & SJ_FLAG_ACCUMULATE) && k != SJ_LTIMES && k != SJ_LPLUSTIMES)
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_ACCUMULATE applies to LTimes and LPlusTimes");
+    if (k == SJ_LTIMES_LPLUS) {
+        // LTimes then LPlusTimes in one pass: FP64, the DIRECT structure
+        if (s->dtype != SJ_F64) return fail(SJ_ERR_UNSUPPORTED, "the fused kernel is FP64 only");
+        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
+            return fail(SJ_ERR_UNSUPPORTED, "the fused kernel has the DIRECT structure only");
+    }
     if ((s->flags & SJ_FLAG_LOADS_CACHED) && (s->flags & SJ_FLAG_LOADS_NONTEMPORAL))
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_LOADS_CACHED and SJ_FLAG_LOADS_NONTEMPORAL exclude each other");
     if ((s->flags & SJ_FLAG_STORES_CACHED) && (s->flags & SJ_FLAG_STORES_NONTEMPORAL))
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_STORES_CACHED and SJ_FLAG_STORES_NONTEMPORAL exclude each other");
 
-    if (k == SJ_LTIMES || k == SJ_LPLUSTIMES) {
+    if (k == SJ_LTIMES || k == SJ_LPLUSTIMES || k == SJ_LTIMES_LPLUS) {
         if (s->layout < SJ_DGZ || s->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
         const int64_t dims[4] = {s->Z, s->G, s->D, s->NM};
         for (int64_t v : dims)
@@ -177,14 +183,15 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         int var = s->variant;
         if (var == SJ_VAR_AUTO) {
             if (s->dtype != SJ_F64) var = SJ_VAR_MFMA;
+            else if (k == SJ_LTIMES_LPLUS) var = SJ_VAR_DIRECT;
             else var = key.I == 1 ? SJ_VAR_MFMA : SJ_VAR_DIRECT;
         }
         if (s->dtype != SJ_F64 && var != SJ_VAR_MFMA)
             return fail(SJ_ERR_INVALID_ARG, "BF16 dtypes need the MFMA variant");
         if (var < SJ_VAR_DIRECT || var > SJ_VAR_MFMA) return fail(SJ_ERR_INVALID_ARG, "variant out of range");
         key.variant = var;
-        const int64_t red = (k == SJ_LTIMES) ? s->D : s->NM;   // reduction length
-        const int64_t outn = (k == SJ_LTIMES) ? s->NM : s->D;  // outputs per column
+        const int64_t red = (k == SJ_LPLUSTIMES) ? s->NM : s->D;   // reduction length (first phase when fused)
+        const int64_t outn = (k == SJ_LPLUSTIMES) ? s->D : s->NM;  // outputs per column (first phase when fused)
         if (var == SJ_VAR_DIRECT) {
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
@@ -196,11 +203,11 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             int un = s->unroll ? s->unroll : 8;
             if (un < 1 || un > 64) return fail(SJ_ERR_INVALID_ARG, "unroll must be in [1, 64]");
             key.unroll = (int32_t)std::min<int64_t>(un, k == SJ_LTIMES ? s->D : s->D);
-            // Accumulators (LTimes) or moments (LPlusTimes) live in registers.
-            const int64_t regs = (k == SJ_LTIMES ? s->NM : s->NM) * vec;
+            // Accumulators (LTimes) or moments (LPlusTimes, both for the fused kernel) live in registers.
+            const int64_t regs = s->NM * vec;
             if (regs > 128) return fail(SJ_ERR_UNSUPPORTED, "NM * tile_n > 128 FP64 values per thread");
-            // Full unrolling while the straight-line body stays moderate.
-            key.full_unroll = (red * outn * vec <= 4096) ? 1 : 0;
+            // Full unrolling while the straight-line body stays moderate (the fused kernel has two phases).
+            key.full_unroll = (red * outn * vec * (k == SJ_LTIMES_LPLUS ? 2 : 1) <= 4096) ? 1 : 0;
             key.tile_k = 0;
             // Rotation pays when consecutive rows are >= 1 MiB apart (measured on MI355X:
             // 8 MiB row stride, 5.35 TB/s ascending vs 6.2 TB/s rotated).
@@ -369,7 +376,7 @@ Geometry key_geometry(const SpecKey &k)
     Geometry g{0, (unsigned)k.block};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
-    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         if (k.variant == SJ_VAR_DIRECT) {
             const int64_t nv = k.B * (k.I / k.tile_n);
             g.grid = (unsigned)((nv + k.block - 1) / k.block);
@@ -424,7 +431,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
     o << "// kernel " << k.kernel << " dtype " << k.dtype << " layout " << k.layout << " variant " << k.variant << "\n";
     o << "typedef " << (k.index64 ? "long long" : "int") << " sj_index_t;\n";
     const char *sfx = k.index64 ? "LL" : "";
-    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         o << "#define SJ_D " << k.D << "\n#define SJ_NM " << k.NM << "\n";
         o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
         o << "#define SJ_BLOCK " << k.block << "\n";
@@ -436,7 +443,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         // for the row kernel, whose lanes read each 128-byte line in two halves (171 us vs 199 us).
         const bool rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1);
         const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
-        int ntl = (k.kernel == SJ_LTIMES && streamed && !rows) ? 1 : 0;
+        int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !rows) ? 1 : 0;
         int nts = streamed ? 1 : 0;
         if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
         if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
@@ -447,8 +454,13 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
               << k.full_unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
-            body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_direct : kTpl_lplustimes_direct;
-            *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_direct" : "sj_lplustimes_direct";
+            if (k.kernel == SJ_LTIMES_LPLUS) {
+                body = kTpl_fused_direct;
+                *name = "sj_ltimes_lplus_direct";
+            } else {
+                body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_direct : kTpl_lplustimes_direct;
+                *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_direct" : "sj_lplustimes_direct";
+            }
         } else if (k.variant == SJ_VAR_STAGED) {
             o << "#define SJ_TILE_N " << k.tile_n << "\n#define SJ_TILE_K " << k.tile_k << "\n";
             body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_staged : kTpl_lplustimes_staged;
@@ -500,7 +512,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";
     }
     if (!body) return fail(SJ_ERR_UNSUPPORTED, "no kernel template for this key");
-    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES) {
+    if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         // one symbol per nesting, so profiles tell the layouts apart
         static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
         *name += std::string("_") + lay[k.layout];

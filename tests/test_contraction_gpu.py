@@ -508,3 +508,87 @@ def test_accumulate_refused_where_unsupported(P):
     with pytest.raises(P.SJError) as e:
         P.sj_generic_run(P.SJ_LTIMES, [x, x, x], layout="DGZ", Z=2, G=2, D=2, NM=2, flags=P.SJ_FLAG_ACCUMULATE)
     assert e.value.status == P.SJ_ERR_UNSUPPORTED
+
+
+def run_fused(P, layout, Z, G, D, NM, L_d, Lp_d, psi_d, want_phi=True, **tile):
+    out_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    phi_d = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda") if want_phi else None
+    h = P.sj_specialize(P.SJ_LTIMES_LPLUS, layout=layout, Z=Z, G=G, D=D, NM=NM, **tile)
+    P.sj_run(h, [L_d, Lp_d, psi_d, out_d] + ([phi_d] if want_phi else []))
+    return out_d, phi_d
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("shape", [(37, 5, 11, 6), (300, 3, 48, 16), (1, 1, 1, 1), (64, 2, 96, 16), (9, 4, 7, 40)],
+                         ids=lambda s: "Z%dG%dD%dNM%d" % s)
+def test_fused_ltimes_lplus(P, orc, layout, shape):
+    """psi' = L+ (L psi) in one pass, against the oracle's two steps.  Bar:
+    |psi'_gpu - psi'_oracle| <= 1e-12 * sum_nm |L+[d,nm]| sum_d' |L[nm,d']| |psi[d']|
+    (phi's own error carried through L+), and phi to the LTimes bar."""
+    Z, G, D, NM = shape
+    L, Lp, psi, _ = contraction_inputs(16, layout, Z, G, D, NM)
+    ref_phi = orc.ltimes(layout, Z, G, D, NM, L, psi)
+    s_phi = orc.ltimes_absscale(layout, Z, G, D, NM, L, psi)
+    ref_out = orc.lplustimes(layout, Z, G, D, NM, Lp, ref_phi)
+    s_out = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, s_phi)
+    out_d, phi_d = run_fused(P, layout, Z, G, D, NM, dev(L), dev(Lp), dev(psi))
+    assert componentwise_err(host(phi_d), ref_phi, s_phi) <= TOL_F64
+    assert componentwise_err(host(out_d), ref_out, s_out) <= TOL_F64
+    out2, _ = run_fused(P, layout, Z, G, D, NM, dev(L), dev(Lp), dev(psi), want_phi=False)
+    assert np.array_equal(host(out2), host(out_d))       # the phi store does not change psi'
+
+
+@pytest.mark.parametrize("layout,tile", [("DGZ", dict(tile_n=2, unroll=4, order=2)), ("ZDG", dict(tile_n=1, unroll=8)),
+                                         ("GDZ", dict(tile_n=2, unroll=16, block=512))])
+def test_fused_matches_separate_bitwise(P, layout, tile):
+    """The fused kernel takes the separate DIRECT kernels' steps: with the same
+    tiles, phi equals LTimes' output and psi' equals LPlusTimes applied to that
+    phi, bit for bit."""
+    Z, G, D, NM = 300, 4, 48, 16
+    L, Lp, psi, _ = contraction_inputs(17, layout, Z, G, D, NM)
+    L_d, Lp_d, psi_d = dev(L), dev(Lp), dev(psi)
+    out_d, phi_d = run_fused(P, layout, Z, G, D, NM, L_d, Lp_d, psi_d, variant=1, **tile)
+    phi_sep = run_ltimes(P, layout, Z, G, D, NM, L_d, psi_d, variant=1, **tile)
+    out_sep = run_lplus(P, layout, Z, G, D, NM, Lp_d, phi_sep, variant=1, **tile)
+    assert np.array_equal(host(phi_d), host(phi_sep))
+    assert np.array_equal(host(out_d), host(out_sep))
+
+
+def test_fused_checks(P):
+    Z, G, D, NM = 8, 2, 4, 3
+    x = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    h = P.sj_specialize(P.SJ_LTIMES_LPLUS, layout="DGZ", Z=Z, G=G, D=D, NM=NM)
+    with pytest.raises(P.SJError) as e:   # psi_out overlaps psi
+        P.sj_run(h, [x, x.data_ptr() + 1024, x.data_ptr() + 2048, x.data_ptr() + 2048])
+    assert e.value.status == P.SJ_ERR_ALIAS
+    with pytest.raises(P.SJError) as e:
+        P.sj_run(h, [x, x, x])
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("layout", ["DGZ", "ZGD"])
+def test_fused_full_size_sampled(P, orc, layout):
+    """Z=32768 G=32 D=96 NM=16, fused, 2048 sampled columns against the oracle's
+    two steps on those columns."""
+    Z, G, D, NM = 32768, 32, 96, 16
+    li = LAYOUTS.index(layout)
+    psi_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+    gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01, li, (D, G, Z))
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    Lp = gen.matrix_sym(0, gen.ARR_LPLUS, D, NM)
+    out_d, phi_d = run_fused(P, layout, Z, G, D, NM, dev(L), dev(Lp), psi_d)
+    rng = np.random.default_rng(18)
+    g = rng.integers(0, G, 2048)
+    z = rng.integers(0, Z, 2048)
+    g[-1], z[-1] = G - 1, Z - 1
+    cols = gen.psi_columns(0, D, G, Z, g, z)
+    ref_phi = orc.ltimes("DGZ", len(g), 1, D, NM, L, cols)
+    s_phi = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols)
+    ref_out = orc.lplustimes("DGZ", len(g), 1, D, NM, Lp, ref_phi).reshape(D, -1)
+    s_out = orc.ltimes_absscale("DGZ", len(g), 1, NM, D, Lp, s_phi).reshape(D, -1)
+    out_log = gen.from_layout(host(out_d), layout, D, G, Z)
+    assert componentwise_err(out_log[:, g, z], ref_out, s_out) <= TOL_F64
+    phi_log = gen.from_layout(host(phi_d), layout, NM, G, Z)
+    assert componentwise_err(phi_log[:, g, z], ref_phi.reshape(NM, -1), s_phi.reshape(NM, -1)) <= TOL_F64
+    del psi_d, out_d, phi_d
+    torch.cuda.empty_cache()
