@@ -99,7 +99,10 @@ typedef enum sj_dtype {
  * innermost storage axis is a column axis (DGZ, DZG, GDZ, ZDG) and the FP64
  * matrix-core row kernel (MFMA) when it is D (GZD, ZGD); BF16 dtypes always
  * use MFMA.  FP64 MFMA with a column axis innermost is the matrix-core column
- * kernel (chosen explicitly, or by a tuner). */
+ * kernel (chosen explicitly, or by a tuner).  The fused SJ_LTIMES_LPLUS has
+ * DIRECT and, for D innermost, the MFMA row structure (AUTO's choice there).
+ * When AUTO's first choice declines a shape (register or LDS limits), the
+ * next structure that accepts it is taken. */
 typedef enum sj_variant {
     SJ_VAR_AUTO = 0,
     SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
@@ -209,7 +212,8 @@ sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *
  *   SJ_LPLUSTIMES: {L+ [D*NM] f64, phi [NM*G*Z] f64, psi_out [D*G*Z] f64}
  *   SJ_LTIMES_LPLUS: {L [NM*D], L+ [D*NM], psi [D*G*Z], psi_out [D*G*Z]} or the same with
  *                  phi [NM*G*Z] appended when the moments are wanted too (all f64); psi_out =
- *                  L+ (L psi) with the moments held in registers (DIRECT structure, FP64)
+ *                  L+ (L psi) with the moments kept on chip (FP64; DIRECT structure, or
+ *                  the matrix-core row structure when D is innermost)
  *   SJ_MLP_FWD:    {theta f32, X [rows*inputs] f32, y [rows] f32}
  *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32,
  *                  workspace [rows*(4*width+2)] f32}

@@ -224,6 +224,15 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
         }
         h->info.load_ms = ms_since(t0);
         h->runnable = true;
+        if (key.kernel == SJ_LTIMES_LPLUS && key.variant == SJ_VAR_MFMA) {
+            // persistent grid: the workgroups resident at once on this device
+            int blocks = 0, cus = 0;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, h->fn, (int)h->geom.block, 0) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, key.device) == hipSuccess &&
+                blocks > 0 && cus > 0)
+                h->geom.grid = (unsigned)std::min<int64_t>(h->geom.grid, (int64_t)blocks * cus);
+            h->info.grid = h->geom.grid;
+        }
         if (precompiled) {
             // resource usage of a code object compiled elsewhere, from the loaded function
             int v = 0;

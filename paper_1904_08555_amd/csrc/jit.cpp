@@ -111,14 +111,21 @@ sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, 
     if (!s || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output");
     if (s->struct_size != sizeof(sj_spec))
         return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size does not match this library's sj_spec");
-    if (!((k == SJ_LTIMES || k == SJ_LPLUSTIMES) && s->variant == SJ_VAR_AUTO && s->dtype == SJ_F64))
+    if (!((k == SJ_LTIMES || k == SJ_LPLUSTIMES || k == SJ_LTIMES_LPLUS) && s->variant == SJ_VAR_AUTO &&
+          s->dtype == SJ_F64))
         return make_key_one(k, s, device, arch, out);
     int64_t B = 0, I = 0;
     if (s->layout >= SJ_DGZ && s->layout <= SJ_ZGD && s->Z >= 1 && s->G >= 1) layout_view(s->layout, s->Z, s->G, &B, &I);
     static const int kRows[3] = {SJ_VAR_MFMA, SJ_VAR_STAGED, SJ_VAR_DIRECT};
     static const int kCols[2] = {SJ_VAR_DIRECT, SJ_VAR_MFMA};
+    static const int kFusedRows[2] = {SJ_VAR_MFMA, SJ_VAR_DIRECT};
+    static const int kFusedCols[1] = {SJ_VAR_DIRECT};
     const int *order = (I == 1) ? kRows : kCols;
-    const int n = (I == 1) ? 3 : 2;
+    int n = (I == 1) ? 3 : 2;
+    if (k == SJ_LTIMES_LPLUS) {
+        order = (I == 1) ? kFusedRows : kFusedCols;
+        n = (I == 1) ? 2 : 1;
+    }
     sj_status st = SJ_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i) {
         sj_spec t = *s;
@@ -147,10 +154,11 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     if ((s->flags & SJ_FLAG_ACCUMULATE) && k != SJ_LTIMES && k != SJ_LPLUSTIMES)
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_ACCUMULATE applies to LTimes and LPlusTimes");
     if (k == SJ_LTIMES_LPLUS) {
-        // LTimes then LPlusTimes in one pass: FP64, the DIRECT structure
+        // LTimes then LPlusTimes in one pass: FP64; the DIRECT structure, or the FP64 matrix-core
+        // row structure when D is innermost (GZD, ZGD)
         if (s->dtype != SJ_F64) return fail(SJ_ERR_UNSUPPORTED, "the fused kernel is FP64 only");
-        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
-            return fail(SJ_ERR_UNSUPPORTED, "the fused kernel has the DIRECT structure only");
+        if (s->variant == SJ_VAR_STAGED)
+            return fail(SJ_ERR_UNSUPPORTED, "the fused kernel has the DIRECT and MFMA (D innermost) structures");
     }
     if ((s->flags & SJ_FLAG_LOADS_CACHED) && (s->flags & SJ_FLAG_LOADS_NONTEMPORAL))
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_LOADS_CACHED and SJ_FLAG_LOADS_NONTEMPORAL exclude each other");
@@ -183,7 +191,6 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         int var = s->variant;
         if (var == SJ_VAR_AUTO) {
             if (s->dtype != SJ_F64) var = SJ_VAR_MFMA;
-            else if (k == SJ_LTIMES_LPLUS) var = SJ_VAR_DIRECT;
             else var = key.I == 1 ? SJ_VAR_MFMA : SJ_VAR_DIRECT;
         }
         if (s->dtype != SJ_F64 && var != SJ_VAR_MFMA)
@@ -239,6 +246,34 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             const int64_t lds = (int64_t)key.tile_n * std::max<int64_t>(key.tile_k + 1, s->NM + 1) * 8;
             if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "STAGED tile exceeds 160 KiB of LDS");
             key.unroll = 0;
+            key.full_unroll = 1;
+        } else if (k == SJ_LTIMES_LPLUS) {
+            // Fused FP64 matrix-core row kernel (D innermost): tile_n = 16-row tiles per wave;
+            // both phases' weight fragments and a per-wave phi tile live in LDS.
+            if (key.I != 1) return fail(SJ_ERR_UNSUPPORTED, "the fused MFMA kernel needs D innermost (GZD, ZGD)");
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            if (s->unroll != 0) return fail(SJ_ERR_INVALID_ARG, "the fused MFMA kernel takes no unroll");
+            key.order = 1;
+            key.block = s->block ? s->block : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            const int64_t bd = (s->D + 15) / 16, bn = (s->NM + 15) / 16;
+            // registers per lane: the prefetched loads (up to 12 blocks x tiles of 4 values), both
+            // phases' accumulators and about 20 more, against 512 / (waves per SIMD the block needs)
+            const int64_t budget = 512 / std::max(1, key.block / 256);
+            auto regs = [&](int64_t rt) {
+                const int64_t pf = std::min<int64_t>(std::max<int64_t>(12 / rt, 1), bd);
+                return 2 * (pf * rt * 4 + rt * bd * 4 + rt * bn * 4) + 20;
+            };
+            int rt = s->tile_n;
+            if (rt == 0) rt = 1;   // measured on MI355X at D=96, NM=16: 336 us (1 tile) vs 347 us (2 tiles)
+            if (rt < 1 || rt > 8) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (16-row tiles per wave) must be in [1, 8]");
+            if (rt * std::max(bd, bn) * 4 > 96) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 96 FP64 values per lane");
+            if (regs(rt) > budget) return fail(SJ_ERR_UNSUPPORTED, "fused MFMA registers exceed what the block size leaves per lane");
+            const int64_t lds = 2 * bd * 4 * bn * 64 * 8 + (int64_t)(key.block / 64) * 16 * rt * (16 * bn + 2) * 8;
+            if (lds > 160 * 1024) return fail(SJ_ERR_UNSUPPORTED, "fused MFMA fragments and phi tiles exceed 160 KiB of LDS");
+            key.tile_n = rt;
+            key.unroll = 0;
+            key.tile_k = 16;
             key.full_unroll = 1;
         } else if (s->dtype == SJ_F64 && key.I > 1) {
             // FP64 matrix-core column contraction: tile_n = columns per lane (1, 2, 4),
@@ -386,6 +421,12 @@ Geometry key_geometry(const SpecKey &k)
             const int64_t tiles = k.B * ((k.I + 16 * k.tile_n - 1) / (16 * k.tile_n));
             const int64_t waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.kernel == SJ_LTIMES_LPLUS) {
+            // persistent: at most one group of tiles per wave; capped at load time to the
+            // workgroups the device holds at once
+            const int64_t groups = (k.B + 16 * k.tile_n - 1) / (16 * k.tile_n);
+            const int64_t waves = k.block / 64;
+            g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const int64_t rows_per_block = (int64_t)(k.block / 64) * 16 * k.tile_n;
             g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
@@ -471,6 +512,10 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
               << k.tile_n << "\n#define SJ_PF " << k.unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
             *name = lt ? "sj_ltimes_cols_mfma" : "sj_lplustimes_cols_mfma";
             body = kTpl_cols_mfma64;
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.kernel == SJ_LTIMES_LPLUS) {
+            o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_RT " << k.tile_n << "\n";
+            *name = "sj_ltimes_lplus_rows_mfma";
+            body = kTpl_fused_rows_mfma64;
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const bool lt = (k.kernel == SJ_LTIMES);
             o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT "

@@ -289,3 +289,35 @@ def test_load_store_policy_flags(P):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co | bad, **base)
         assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
+def test_fused_structures(P):
+    """LTimes followed by LPlusTimes in one kernel: DIRECT for a column axis
+    innermost, the matrix-core row structure for D innermost, DIRECT again
+    where the row structure's LDS limit declines the shape; STAGED, the column
+    MFMA structure and accumulation are refused."""
+    co = P.SJ_FLAG_COMPILE_ONLY
+
+    def name(layout, **kw):
+        h = P.sj_specialize(P.SJ_LTIMES_LPLUS, layout=layout, flags=co | kw.pop("flags", 0), **kw)
+        return P.sj_handle_info(h)["kernel_name"]
+    base = dict(Z=64, G=8, D=96, NM=16)
+    assert name("DGZ", **base) == "sj_ltimes_lplus_direct_dgz"
+    assert name("ZGD", **base) == "sj_ltimes_lplus_rows_mfma_zgd"
+    assert name("GZD", variant=P.SJ_VAR_DIRECT, **base) == "sj_ltimes_lplus_direct_gzd"
+    # 2 x 13 x 4 x 4 weight fragments of 512 bytes exceed the LDS: the next structure takes it
+    assert name("ZGD", Z=64, G=8, D=200, NM=49) == "sj_ltimes_lplus_direct_zgd"
+    src = P.sj_emit_source(P.SJ_LTIMES_LPLUS, layout="ZGD", flags=co, **base)
+    assert "#define SJ_NT_LOAD 0" in src and "#define SJ_NT_STORE 1" in src and "#define SJ_RT 1" in src
+    for bad, status in ((dict(layout="ZGD", variant=P.SJ_VAR_STAGED), P.SJ_ERR_UNSUPPORTED),
+                        (dict(layout="DGZ", variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED),
+                        (dict(layout="ZGD", variant=P.SJ_VAR_MFMA, D=200, NM=49), P.SJ_ERR_UNSUPPORTED),
+                        (dict(layout="ZGD", variant=P.SJ_VAR_MFMA, tile_n=9), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZGD", variant=P.SJ_VAR_MFMA, unroll=2), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZGD", flags=P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZGD", dtype=P.SJ_BF16), P.SJ_ERR_UNSUPPORTED)):
+        spec = dict(base, **bad)
+        spec["flags"] = co | spec.get("flags", 0)
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_LTIMES_LPLUS, **spec)
+        assert e.value.status == status, bad

@@ -554,6 +554,24 @@ def test_fused_matches_separate_bitwise(P, layout, tile):
     assert np.array_equal(host(out_d), host(out_sep))
 
 
+@pytest.mark.parametrize("layout,tile", [("ZGD", dict(tile_n=2)), ("GZD", dict(tile_n=1)), ("ZGD", dict(tile_n=4, block=512)),
+                                         ("GZD", dict(tile_n=2, block=64))])
+@pytest.mark.parametrize("shape", [(300, 4, 48, 16), (37, 3, 11, 21)], ids=lambda s: "Z%dG%dD%dNM%d" % s)
+def test_fused_rows_matches_separate_bitwise(P, layout, tile, shape):
+    """D innermost: the fused matrix-core row kernel runs the separate row
+    kernels' MFMA sequences (phase 2 reads the moments from LDS instead of HBM),
+    so with the same tiles phi and psi' equal theirs bit for bit, ragged D and
+    NM included."""
+    Z, G, D, NM = shape
+    L, Lp, psi, _ = contraction_inputs(19, layout, Z, G, D, NM)
+    L_d, Lp_d, psi_d = dev(L), dev(Lp), dev(psi)
+    out_d, phi_d = run_fused(P, layout, Z, G, D, NM, L_d, Lp_d, psi_d, variant=3, **tile)
+    phi_sep = run_ltimes(P, layout, Z, G, D, NM, L_d, psi_d, variant=3, **tile)
+    out_sep = run_lplus(P, layout, Z, G, D, NM, Lp_d, phi_sep, variant=3, **tile)
+    assert np.array_equal(host(phi_d), host(phi_sep))
+    assert np.array_equal(host(out_d), host(out_sep))
+
+
 def test_fused_checks(P):
     Z, G, D, NM = 8, 2, 4, 3
     x = torch.zeros(4096, dtype=torch.float64, device="cuda")
