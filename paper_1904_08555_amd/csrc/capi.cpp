@@ -224,7 +224,7 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
         }
         h->info.load_ms = ms_since(t0);
         h->runnable = true;
-        if (key.kernel == SJ_LTIMES_LPLUS && key.variant == SJ_VAR_MFMA) {
+        if (h->geom.persistent) {
             // persistent grid: the workgroups resident at once on this device
             int blocks = 0, cus = 0;
             if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, h->fn, (int)h->geom.block, 0) == hipSuccess &&

@@ -224,7 +224,7 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             if ((k == SJ_LTIMES ? s->D : s->D) < 2 * key.unroll) order = 1;  // fewer than two row groups
             key.order = order;
         } else if (var == SJ_VAR_STAGED) {
-            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "this structure has no order 2");
             key.order = 1;
             if (key.I != 1) return fail(SJ_ERR_UNSUPPORTED, "STAGED needs a layout with D innermost (GZD, ZGD)");
             key.block = s->block ? s->block : 256;
@@ -248,29 +248,41 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             key.unroll = 0;
             key.full_unroll = 1;
         } else if (k == SJ_LTIMES_LPLUS) {
-            // Fused FP64 matrix-core row kernel (D innermost): tile_n = 16-row tiles per wave;
-            // both phases' weight fragments and a per-wave phi tile live in LDS.
+            // Fused FP64 matrix-core row kernel (D innermost): tile_n = 16-row tiles per wave (per
+            // group); both phases' weight fragments and per-wave tiles live in LDS.  order 1 = lanes
+            // read psi rows directly, order 2 = contiguous runs of psi, phi and out staged in LDS.
             if (key.I != 1) return fail(SJ_ERR_UNSUPPORTED, "the fused MFMA kernel needs D innermost (GZD, ZGD)");
-            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            if (s->order < 0 || s->order > 2) return fail(SJ_ERR_INVALID_ARG, "order must be 0, 1 or 2");
             if (s->unroll != 0) return fail(SJ_ERR_INVALID_ARG, "the fused MFMA kernel takes no unroll");
-            key.order = 1;
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
-            const int64_t bd = (s->D + 15) / 16, bn = (s->NM + 15) / 16;
-            // registers per lane: the prefetched loads (up to 12 blocks x tiles of 4 values), both
-            // phases' accumulators and about 20 more, against 512 / (waves per SIMD the block needs)
-            const int64_t budget = 512 / std::max(1, key.block / 256);
-            auto regs = [&](int64_t rt) {
-                const int64_t pf = std::min<int64_t>(std::max<int64_t>(12 / rt, 1), bd);
-                return 2 * (pf * rt * 4 + rt * bd * 4 + rt * bn * 4) + 20;
-            };
             int rt = s->tile_n;
             if (rt == 0) rt = 1;   // measured on MI355X at D=96, NM=16: 336 us (1 tile) vs 347 us (2 tiles)
             if (rt < 1 || rt > 8) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (16-row tiles per wave) must be in [1, 8]");
+            const int64_t bd = (s->D + 15) / 16, bn = (s->NM + 15) / 16;
             if (rt * std::max(bd, bn) * 4 > 96) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 96 FP64 values per lane");
-            if (regs(rt) > budget) return fail(SJ_ERR_UNSUPPORTED, "fused MFMA registers exceed what the block size leaves per lane");
-            const int64_t lds = 2 * bd * 4 * bn * 64 * 8 + (int64_t)(key.block / 64) * 16 * rt * (16 * bn + 2) * 8;
-            if (lds > 160 * 1024) return fail(SJ_ERR_UNSUPPORTED, "fused MFMA fragments and phi tiles exceed 160 KiB of LDS");
+            // registers per lane: the loads in flight, both phases' accumulators and about 20 more,
+            // against 512 / (waves per SIMD the block needs)
+            const int64_t budget = 512 / std::max(1, key.block / 256);
+            const int64_t frags = 2 * bd * 4 * bn * 64 * 8;
+            auto fits = [&](int order, const char **why) {
+                const int64_t pf = std::min<int64_t>(std::max<int64_t>(12 / rt, 1), bd);
+                const int64_t nj = (16 * rt * s->D / 2 + 63) / 64;
+                const int64_t inflight = (order == 2) ? 2 * nj : pf * rt * 4;
+                const int64_t tiles = (order == 2) ? 16 * rt * ((16 * bd + 2) + (16 * bn + 2)) * 8 : 16 * rt * (16 * bn + 2) * 8;
+                if (order == 2 && (s->D % 2 != 0 || s->NM % 2 != 0)) return *why = "order 2 needs even D and NM", false;
+                if (order == 2 && nj > 32) return *why = "order 2 holds at most 32 loads per lane", false;
+                if (2 * (inflight + rt * bd * 4 + rt * bn * 4) + 20 > budget)
+                    return *why = "fused MFMA registers exceed what the block size leaves per lane", false;
+                if (frags + (int64_t)(key.block / 64) * tiles > 160 * 1024)
+                    return *why = "fused MFMA fragments and tiles exceed 160 KiB of LDS", false;
+                return true;
+            };
+            const char *why = "";
+            int order = s->order;
+            if (order == 0) order = fits(2, &why) ? 2 : 1;
+            if (!fits(order, &why)) return fail(SJ_ERR_UNSUPPORTED, why);
+            key.order = order;
             key.tile_n = rt;
             key.unroll = 0;
             key.tile_k = 16;
@@ -305,27 +317,57 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             key.tile_k = 4;
             key.full_unroll = 0;
         } else if (s->dtype == SJ_F64) {
-            // FP64 matrix-core row contraction (D innermost): tile_n = 16-row tiles per wave.
-            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
-            key.order = 1;
-            key.block = s->block ? s->block : 256;
-            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            // FP64 matrix-core row contraction (D innermost): tile_n = 16-row tiles per wave (per
+            // group); order 1 = every lane reads its operands from HBM, order 2 = a group's rows are
+            // read and written as one contiguous run staged through LDS, persistent grid.
+            if (s->order < 0 || s->order > 2) return fail(SJ_ERR_INVALID_ARG, "order must be 0, 1 or 2");
+            if (s->block && !valid_block(s->block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            if (s->tile_n < 0 || s->tile_n > 8) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (16-row tiles per wave) must be in [1, 8]");
             const int64_t ob = (outn + 15) / 16, kb = (red + 15) / 16;
-            int rt = s->tile_n;
-            if (rt == 0) rt = (2 * ob * 4 <= 96) ? 2 : 1;   // measured best on MI355X at D=96, NM=16
-            if (rt < 1 || rt > 8) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (16-row tiles per wave) must be in [1, 8]");
-            if (rt * ob * 4 > 96) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 96 FP64 values per lane");
-            key.tile_n = rt;
             const int64_t nfrag = kb * 4 * ob;
             key.unroll = nfrag <= 32 ? 1 : 0;       // W fragments in registers (1) or LDS (0)
             if (!key.unroll && nfrag * 64 * 8 > 160 * 1024)
                 return fail(SJ_ERR_UNSUPPORTED, "MFMA weight fragments exceed 160 KiB of LDS");
+            // order 2: even row lengths, at most 32 16-byte loads per lane in flight, LDS within 160 KiB
+            auto run_ok = [&](int64_t rt, int block, const char **why) {
+                const int64_t pitch = std::max<int64_t>(16 * kb, outn) + 2;
+                const int64_t lds = (int64_t)(block / 64) * 16 * rt * pitch * 8 + (key.unroll ? 0 : nfrag * 64 * 8);
+                if (red % 2 != 0 || outn % 2 != 0) return *why = "order 2 needs even D and NM", false;
+                if (rt * ob * 4 > 96) return *why = "MFMA accumulators exceed 96 FP64 values per lane", false;
+                if ((16 * rt * red / 2 + 63) / 64 > 32) return *why = "order 2 holds at most 32 loads per lane", false;
+                if (lds > 160 * 1024) return *why = "order 2 tiles exceed 160 KiB of LDS", false;
+                return true;
+            };
+            int order = s->order, rt = s->tile_n, block = s->block;
+            const char *why = "";
+            if (order != 1) {
+                // defaults measured on MI355X at D=96, NM=16 (ZGD): reduction-heavy rows (LTimes)
+                // 2 tiles per wave in 256-thread workgroups, 163 us; output-heavy rows (LPlusTimes)
+                // 1 tile in 64-thread workgroups, 153 us; the direct form takes 178 and 157 us
+                static const int kTry[3][2] = {{2, 256}, {1, 256}, {1, 64}};
+                int first = (red > outn || !key.unroll) ? 0 : 2;   // weights in LDS: share them over a wider block
+                bool found = false;
+                for (int i = first; i < 3 && !found; ++i) {
+                    const int r = rt ? rt : kTry[i][0], b = block ? block : kTry[i][1];
+                    if (run_ok(r, b, &why)) { rt = r; block = b; found = true; }
+                }
+                if (!found && order == 2) return fail(SJ_ERR_UNSUPPORTED, why);
+                order = found ? 2 : 1;
+            }
+            if (order == 1) {
+                if (rt == 0) rt = (2 * ob * 4 <= 96) ? 2 : 1;
+                if (block == 0) block = 256;
+                if (rt * ob * 4 > 96) return fail(SJ_ERR_UNSUPPORTED, "MFMA accumulators exceed 96 FP64 values per lane");
+            }
+            key.block = block;
+            key.order = order;
+            key.tile_n = rt;
             key.tile_k = 16;
             key.full_unroll = 1;
         } else {
             // BF16 matrix-core LTimes, column axis contiguous: one 32-column tile per wave.
             if (key.I == 1) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes needs a layout with a column axis innermost");
-            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "order 2 applies to DIRECT only");
+            if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "this structure has no order 2");
             key.order = 1;
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
@@ -408,7 +450,7 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
 
 Geometry key_geometry(const SpecKey &k)
 {
-    Geometry g{0, (unsigned)k.block};
+    Geometry g{0, (unsigned)k.block, 0};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
@@ -427,6 +469,12 @@ Geometry key_geometry(const SpecKey &k)
             const int64_t groups = (k.B + 16 * k.tile_n - 1) / (16 * k.tile_n);
             const int64_t waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
+            g.persistent = 1;
+        } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.order == 2) {
+            const int64_t groups = (k.B + 16 * k.tile_n - 1) / (16 * k.tile_n);
+            const int64_t waves = k.block / 64;
+            g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
+            g.persistent = 1;
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const int64_t rows_per_block = (int64_t)(k.block / 64) * 16 * k.tile_n;
             g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
@@ -479,12 +527,13 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         // streaming hint: skip cache retention when every fetched line is used at once
         // Load and store policy: explicit flags, else the default measured on MI355X at
         // Z=32768 G=32 D=96 NM=16: nontemporal stores for every streamed output;
-        // nontemporal loads only for LTimes' column kernels (LTimes DGZ 166 us vs 177 us with
-        // ordinary loads); ordinary loads for LPlusTimes (DGZ 151 us vs 186 us nontemporal) and
-        // for the row kernel, whose lanes read each 128-byte line in two halves (171 us vs 199 us).
-        const bool rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1);
+        // nontemporal loads for LTimes' column kernels (LTimes DGZ 166 us vs 177 us with ordinary
+        // loads) and its LDS-staged row kernel (163 us vs 174 us); ordinary loads for LPlusTimes
+        // (DGZ 151 us vs 186 us nontemporal) and for the direct row kernels, whose lanes read
+        // each 128-byte line in two halves (171 us vs 199 us).
+        const bool direct_rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1 && k.order != 2);
         const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
-        int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !rows) ? 1 : 0;
+        int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !direct_rows) ? 1 : 0;
         int nts = streamed ? 1 : 0;
         if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
         if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
@@ -514,14 +563,19 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             body = kTpl_cols_mfma64;
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.kernel == SJ_LTIMES_LPLUS) {
             o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_RT " << k.tile_n << "\n";
-            *name = "sj_ltimes_lplus_rows_mfma";
-            body = kTpl_fused_rows_mfma64;
+            *name = (k.order == 2) ? "sj_ltimes_lplus_rows_mfma_lds" : "sj_ltimes_lplus_rows_mfma";
+            body = (k.order == 2) ? kTpl_fused_rows_lds_mfma64 : kTpl_fused_rows_mfma64;
         } else if (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64) {
             const bool lt = (k.kernel == SJ_LTIMES);
             o << "#define SJ_ROWS " << k.B << sfx << "\n#define SJ_K " << (lt ? k.D : k.NM) << "\n#define SJ_NOUT "
               << (lt ? k.NM : k.D) << "\n#define SJ_RT " << k.tile_n << "\n#define SJ_WREG " << k.unroll << "\n";
-            *name = lt ? "sj_ltimes_rows_mfma" : "sj_lplustimes_rows_mfma";
-            body = kTpl_rows_mfma64;
+            if (k.order == 2) {
+                *name = lt ? "sj_ltimes_rows_mfma_lds" : "sj_lplustimes_rows_mfma_lds";
+                body = kTpl_rows_lds_mfma64;
+            } else {
+                *name = lt ? "sj_ltimes_rows_mfma" : "sj_lplustimes_rows_mfma";
+                body = kTpl_rows_mfma64;
+            }
         } else if (k.variant == SJ_VAR_MFMA) {
             *name = (k.dtype == SJ_BF16X3) ? "sj_ltimes_bf16x3" : "sj_ltimes_bf16";
             if (k.tile_n == 4) *name += "w";

@@ -58,6 +58,7 @@ inline int64_t mlp_nparams(int64_t inputs, int64_t width) { return width * input
 struct Geometry {
     unsigned grid;
     unsigned block;
+    int persistent;   // the kernel loops over its work: the grid is capped at load time to the resident workgroups
 };
 Geometry key_geometry(const SpecKey &key);
 

@@ -15,7 +15,8 @@ NM ~ U{4, 9, 16, 36, 64}, dtype ~ U{FP64, BF16x3}.  Candidates:
   FP64, column axis innermost (DGZ, DZG, GDZ, ZDG): DIRECT, tile_n in {1, 2},
       order in {ascending, rotated}, unroll 8, block 256; FP64-MFMA columns
       with default tiles, order in {ascending, rotated};
-  FP64, D innermost (GZD, ZGD): FP64-MFMA rows, tile_n in {1, 2, 4};
+  FP64, D innermost (GZD, ZGD): FP64-MFMA rows, tile_n in {1, 2, 4}, block
+      256, default operand path (LDS-staged runs where they fit);
   BF16x3 (column layouts only): columns per lane in {1, 4} (4 when it
       divides the contiguous extent), block 256.
 The cost of a candidate is the median of 5 timed launches of one LTimes (after
@@ -116,8 +117,23 @@ def resolved(shape: dict, cand: dict) -> dict:
         r["order"] = r["order"] or (2 if far else 1)
         r["width"], r["acc"] = 16 * t, ob * 4 * t
     else:
-        rt = cand.get("tile_n", 0) or (2 if 8 * ob <= 96 else 1)
-        r["tile"], r["unroll"], r["order"] = rt, 1, 1
+        # row kernel: the LDS-staged form (order 2) when the rows are even and its
+        # registers and LDS allow, else lanes read their operands directly (order 1)
+        D = shape["D"]
+        kb = (D + 15) // 16
+        wreg = kb * 4 * ob <= 32
+        rt = cand.get("tile_n", 0)
+        block = r["block"]
+
+        def run_ok(t):
+            lds = (block // 64) * 16 * t * (max(16 * kb, NM) + 2) * 8 + (0 if wreg else kb * 4 * ob * 512)
+            return D % 2 == 0 and NM % 2 == 0 and t * ob * 4 <= 96 and (8 * t * D + 63) // 64 <= 32 and lds <= 160 * 1024
+        order = cand.get("order", 0)
+        if order != 1 and run_ok(rt or (2 if cand.get("block", 0) in (0, 256) else 1)):
+            rt, order = rt or (2 if cand.get("block", 0) in (0, 256) else 1), 2
+        else:
+            rt, order = rt or (2 if 8 * ob <= 96 else 1), 1
+        r["tile"], r["unroll"], r["order"] = rt, 1, order
         r["width"], r["acc"] = 1, rt * ob * 4
     return r
 

@@ -15,9 +15,11 @@ The candidate set (at most 33 per kernel and layout):
     in {1, 2, 4} dividing the extent and unroll (reduction steps per group of
     loads) in {2, 4, 8}, default order  (<= 9)
   * innermost axis is D (GZD, ZGD): STAGED with tile_k in {8, 16, 32},
-    block 256, tile_n in {256, 512}; FP64 MFMA with 16-row tiles per wave in
-    {1, 2, 4}, block in {256, 512} and ordinary or nontemporal loads;
-    DIRECT with tile_n 1, unroll 8  (<= 19)
+    block 256, tile_n in {256, 512}; FP64 MFMA, ordinary or nontemporal
+    loads, with operands read by every lane (order 1: 16-row tiles per wave
+    in {1, 2, 4}, block in {256, 512}) or read as contiguous runs staged in
+    LDS (order 2: tiles x block in {1x64, 1x256, 2x128, 2x256}); DIRECT with
+    tile_n 1, unroll 8  (<= 27)
   * BF16 dtypes: columns per lane in {1, 4} (4 when it divides the extent),
     block in {256, 512}  (<= 4)
 Candidates that the specializer rejects for a shape (register or LDS limits)
@@ -65,10 +67,12 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
         for tk in (8, 16, 32):
             for tn in (256, 512):
                 out.append(dict(variant=sj.SJ_VAR_STAGED, tile_n=tn, tile_k=tk, block=256))
-        for rt in (1, 2, 4):
-            for block in (256, 512):
-                for fl in (0, sj.SJ_FLAG_LOADS_NONTEMPORAL):
-                    out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, flags=fl))
+        for fl in (0, sj.SJ_FLAG_LOADS_NONTEMPORAL):
+            for rt in (1, 2, 4):      # operands read by every lane straight from HBM
+                for block in (256, 512):
+                    out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=1, flags=fl))
+            for rt, block in ((1, 64), (1, 256), (2, 128), (2, 256)):   # contiguous runs staged in LDS
+                out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=2, flags=fl))
         out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=1, unroll=8, block=256))
     return out
 

@@ -71,7 +71,7 @@ def test_emitted_source_is_self_contained(P):
 @pytest.mark.parametrize("bad", [
     dict(Z=0), dict(G=-1), dict(D=2 ** 31), dict(NM=0), dict(layout=6), dict(dtype=9),
     dict(block=100), dict(block=2048), dict(tile_n=3, variant=1, layout="DGZ"), dict(tile_n=9),
-    dict(unroll=0, variant=1, tile_n=5), dict(order=3, variant=1, layout="DGZ"), dict(order=2),
+    dict(unroll=0, variant=1, tile_n=5), dict(order=3, variant=1, layout="DGZ"), dict(order=2, D=9), dict(order=2, variant=2),
     dict(variant=2, layout="DGZ"), dict(variant=9),
 ])
 def test_invalid_specs_rejected(P, bad):
@@ -271,15 +271,19 @@ def test_load_store_policy_flags(P):
 
     def src(layout, flags=0, **kw):
         return P.sj_emit_source(P.SJ_LTIMES, layout=layout, flags=co | flags, **dict(base, **kw))
-    rows = src("ZGD", variant=P.SJ_VAR_MFMA)
+    rows = src("ZGD", variant=P.SJ_VAR_MFMA, order=1)
     assert "#define SJ_NT_LOAD 0" in rows and "#define SJ_NT_STORE 1" in rows
+    runs = src("ZGD", variant=P.SJ_VAR_MFMA)      # LDS-staged row kernel: whole lines per load
+    assert "rows_mfma_lds" in runs and "#define SJ_NT_LOAD 1" in runs and "#define SJ_NT_STORE 1" in runs
+    lplus_runs = P.sj_emit_source(P.SJ_LPLUSTIMES, layout="ZGD", flags=co, **base)
+    assert "rows_mfma_lds" in lplus_runs and "#define SJ_NT_LOAD 0" in lplus_runs
     cols = src("DGZ")
     assert "#define SJ_NT_LOAD 1" in cols and "#define SJ_NT_STORE 1" in cols
     lplus = P.sj_emit_source(P.SJ_LPLUSTIMES, layout="DGZ", flags=co, **base)
     assert "#define SJ_NT_LOAD 0" in lplus and "#define SJ_NT_STORE 1" in lplus
     mixed = src("DGZ", P.SJ_FLAG_STORES_CACHED)
     assert "#define SJ_NT_LOAD 1" in mixed and "#define SJ_NT_STORE 0" in mixed
-    mixed = src("ZGD", P.SJ_FLAG_LOADS_NONTEMPORAL | P.SJ_FLAG_STORES_CACHED, variant=P.SJ_VAR_MFMA)
+    mixed = src("ZGD", P.SJ_FLAG_LOADS_NONTEMPORAL | P.SJ_FLAG_STORES_CACHED, variant=P.SJ_VAR_MFMA, order=1)
     assert "#define SJ_NT_LOAD 1" in mixed and "#define SJ_NT_STORE 0" in mixed
     h0 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co, **base)
     h1 = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", flags=co | P.SJ_FLAG_STORES_CACHED, **base)
@@ -303,12 +307,14 @@ def test_fused_structures(P):
         return P.sj_handle_info(h)["kernel_name"]
     base = dict(Z=64, G=8, D=96, NM=16)
     assert name("DGZ", **base) == "sj_ltimes_lplus_direct_dgz"
-    assert name("ZGD", **base) == "sj_ltimes_lplus_rows_mfma_zgd"
+    assert name("ZGD", **base) == "sj_ltimes_lplus_rows_mfma_lds_zgd"
+    assert name("ZGD", order=1, **base) == "sj_ltimes_lplus_rows_mfma_zgd"
+    assert name("ZGD", Z=64, G=8, D=95, NM=16) == "sj_ltimes_lplus_rows_mfma_zgd"   # odd D: direct operand reads
     assert name("GZD", variant=P.SJ_VAR_DIRECT, **base) == "sj_ltimes_lplus_direct_gzd"
     # 2 x 13 x 4 x 4 weight fragments of 512 bytes exceed the LDS: the next structure takes it
     assert name("ZGD", Z=64, G=8, D=200, NM=49) == "sj_ltimes_lplus_direct_zgd"
     src = P.sj_emit_source(P.SJ_LTIMES_LPLUS, layout="ZGD", flags=co, **base)
-    assert "#define SJ_NT_LOAD 0" in src and "#define SJ_NT_STORE 1" in src and "#define SJ_RT 1" in src
+    assert "#define SJ_NT_LOAD 1" in src and "#define SJ_NT_STORE 1" in src and "#define SJ_RT 1" in src
     for bad, status in ((dict(layout="ZGD", variant=P.SJ_VAR_STAGED), P.SJ_ERR_UNSUPPORTED),
                         (dict(layout="DGZ", variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED),
                         (dict(layout="ZGD", variant=P.SJ_VAR_MFMA, D=200, NM=49), P.SJ_ERR_UNSUPPORTED),

@@ -260,17 +260,21 @@ def test_same_key_same_handle_and_stats(P):
     assert info["kernel_name"] == "sj_ltimes_direct_zdg" and info["load_ms"] > 0 and info["scratch_bytes"] == 0
 
 
-MFMA_SHAPES = [(150, 3, 37, 9), (64, 4, 96, 16), (33, 1, 5, 3), (16, 1, 16, 16), (40, 2, 17, 20), (7, 3, 128, 64)]
+MFMA_SHAPES = [(150, 3, 37, 9), (64, 4, 96, 16), (33, 1, 5, 3), (16, 1, 16, 16), (40, 2, 17, 20), (7, 3, 128, 64),
+               (150, 3, 38, 10), (21, 5, 24, 18)]
 
 
 @pytest.mark.parametrize("layout", ["GZD", "ZGD"])
 @pytest.mark.parametrize("shape", MFMA_SHAPES, ids=lambda s: "Z%dG%dD%dNM%d" % s)
-@pytest.mark.parametrize("tile", [dict(), dict(tile_n=1, block=64), dict(tile_n=2, block=512), dict(tile_n=4, block=128)],
-                         ids=["default", "t1b64", "t2b512", "t4b128"])
+@pytest.mark.parametrize("tile", [dict(), dict(tile_n=1, block=64), dict(tile_n=2, block=512), dict(tile_n=4, block=128),
+                                  dict(order=1), dict(tile_n=2, block=64, order=2), dict(tile_n=1, block=512, order=2)],
+                         ids=["default", "t1b64", "t2b512", "t4b128", "o1", "t2b64o2", "t1b512o2"])
 def test_mfma64_rows(P, orc, layout, shape, tile):
-    """FP64 matrix-core row kernels (D innermost): ragged rows, odd and
-    non-multiple-of-16 reduction lengths, output counts not multiple of 16,
-    weights in registers and in LDS (D=128, NM=64)."""
+    """FP64 matrix-core row kernels (D innermost), both operand paths (order 1:
+    lanes read rows directly; order 2: contiguous runs staged through LDS,
+    even D and NM only): ragged rows, odd and non-multiple-of-16 reduction
+    lengths, output counts not multiple of 16, weights in registers and in LDS
+    (D=128, NM=64)."""
     Z, G, D, NM = shape
     L, Lp, psi, phi_in = contraction_inputs(8, layout, Z, G, D, NM)
     try:
@@ -290,6 +294,30 @@ def test_mfma64_rows(P, orc, layout, shape, tile):
     ref2 = orc.lplustimes(layout, Z, G, D, NM, Lp, phi_in)
     scale2 = orc.ltimes_absscale(layout, Z, G, NM, D, Lp, phi_in)
     assert componentwise_err(got2, ref2, scale2) <= TOL_F64
+
+
+@pytest.mark.parametrize("layout", ["GZD", "ZGD"])
+@pytest.mark.parametrize("shape", [(150, 3, 38, 10), (64, 4, 96, 16), (21, 5, 24, 18), (1, 1, 2, 2)],
+                         ids=lambda s: "Z%dG%dD%dNM%d" % s)
+@pytest.mark.parametrize("tile", [dict(tile_n=1), dict(tile_n=2, block=64)], ids=["t1", "t2b64"])
+def test_mfma64_rows_orders_bitwise(P, layout, shape, tile):
+    """The LDS-staged row kernel (order 2) runs the MFMA sequences of the
+    direct row kernel (order 1): identical results, bit for bit, for LTimes,
+    LPlusTimes and accumulation."""
+    Z, G, D, NM = shape
+    L, Lp, psi, phi_in = contraction_inputs(20, layout, Z, G, D, NM)
+    L_d, Lp_d, psi_d, phi_d = dev(L), dev(Lp), dev(psi), dev(phi_in)
+    for kern, W_d, x_d, n_out in ((P.SJ_LTIMES, L_d, psi_d, NM), (P.SJ_LPLUSTIMES, Lp_d, phi_d, D)):
+        outs = []
+        for order in (1, 2):
+            for flags in (0, P.SJ_FLAG_ACCUMULATE):
+                h = P.sj_specialize(kern, layout=layout, Z=Z, G=G, D=D, NM=NM, variant=P.SJ_VAR_MFMA, order=order,
+                                    flags=flags, **tile)
+                assert P.sj_handle_info(h)["kernel_name"].endswith(("_lds_" if order == 2 else "_mfma_") + layout.lower())
+                o = torch.full((n_out * G * Z,), 0.25, dtype=torch.float64, device="cuda")
+                P.sj_run(h, [W_d, x_d, o])
+                outs.append(host(o))
+        assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
 
 
 def test_mfma64_full_size_sampled(P, orc):
@@ -555,14 +583,18 @@ def test_fused_matches_separate_bitwise(P, layout, tile):
 
 
 @pytest.mark.parametrize("layout,tile", [("ZGD", dict(tile_n=2)), ("GZD", dict(tile_n=1)), ("ZGD", dict(tile_n=4, block=512)),
-                                         ("GZD", dict(tile_n=2, block=64))])
-@pytest.mark.parametrize("shape", [(300, 4, 48, 16), (37, 3, 11, 21)], ids=lambda s: "Z%dG%dD%dNM%d" % s)
+                                         ("GZD", dict(tile_n=2, block=64)), ("ZGD", dict(tile_n=1, order=1)),
+                                         ("GZD", dict(tile_n=2, block=128, order=2))])
+@pytest.mark.parametrize("shape", [(300, 4, 48, 16), (37, 3, 11, 21), (37, 3, 10, 22), (5, 3, 2, 2)],
+                         ids=lambda s: "Z%dG%dD%dNM%d" % s)
 def test_fused_rows_matches_separate_bitwise(P, layout, tile, shape):
     """D innermost: the fused matrix-core row kernel runs the separate row
     kernels' MFMA sequences (phase 2 reads the moments from LDS instead of HBM),
     so with the same tiles phi and psi' equal theirs bit for bit, ragged D and
     NM included."""
     Z, G, D, NM = shape
+    if tile.get("order") == 2 and (D % 2 or NM % 2):
+        pytest.skip("order 2 needs even D and NM")
     L, Lp, psi, _ = contraction_inputs(19, layout, Z, G, D, NM)
     L_d, Lp_d, psi_d = dev(L), dev(Lp), dev(psi)
     out_d, phi_d = run_fused(P, layout, Z, G, D, NM, L_d, Lp_d, psi_d, variant=3, **tile)
