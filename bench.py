@@ -52,10 +52,15 @@ MEASURED_TRAFFIC = {
 }
 
 
+def source_sha1(P, kernel, spec):
+    """SHA-1 of the emitted source of a specialization: names the exact kernel that counters were taken on."""
+    import hashlib
+    return hashlib.sha1(P.sj_emit_source(kernel, spec).encode()).hexdigest()
+
+
 def measured_traffic(P, kernel, spec):
     """HBM bytes per launch from the counters if they were taken on this exact kernel source, else None."""
-    import hashlib
-    return MEASURED_TRAFFIC.get(hashlib.sha1(P.sj_emit_source(kernel, spec).encode()).hexdigest())
+    return MEASURED_TRAFFIC.get(source_sha1(P, kernel, spec))
 
 
 def algorithmic_bytes(Z, G, D, NM, esz=8):
@@ -82,7 +87,7 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "gpurun_out/tuned_moments.json) instead of tuning")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused"),
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -112,6 +117,8 @@ def main():
         return bench_copy(a)
     if a.workload == "fused":
         return bench_fused(a)
+    if a.workload == "values":
+        return bench_values(a)
     return bench_moments(a)
 
 
@@ -280,7 +287,8 @@ def bench_moments(a):
         jit[f"{key[1]}_{key[0]}"] = dict(kernel=info["kernel_name"], variant=info["variant"], tile_n=info["tile_n"],
                                          tile_k=info["tile_k"], unroll=info["unroll"], block=info["block"],
                                          vgprs=info["vgprs"], scratch=info["scratch_bytes"],
-                                         occupancy=info["occupancy"], lds=info["lds_bytes"])
+                                         occupancy=info["occupancy"], lds=info["lds_bytes"],
+                                         src_sha1=source_sha1(P, kid, s), traffic=measured_traffic(P, kid, s))
     # cold specialization cost: ten keys never compiled before, in this process
     cold = []
     for i in range(10):
@@ -512,7 +520,8 @@ def bench_batched(a):
         "roofline": {"bound": "hbm", "achieved": round(nbytes / (mean * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(P, P.SJ_BGEMM, P.make_spec(**tile)),
-                     "kernel": info["kernel_name"], "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes},
+                     "kernel": info["kernel_name"], "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes,
+                     "src_sha1": source_sha1(P, P.SJ_BGEMM, P.make_spec(**tile))},
         "graph_us_median": round(med * 1e3, 2), "direct_launch_us_median": round(statistics.median(run_per) * 1e3, 2),
         "host_wall_ms_per_step_with_scratch_write": round(t_total * 1e3 / a.steps, 4),
         "generic_us": round(gmed * 1e3, 2),
@@ -577,6 +586,84 @@ def bench_bf16(a):
         "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": best["frac"], "traffic": None, "kernel": best["kernel"], "bytes_per_launch": b32},
         "modes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_values(a):
+    """LTimes and LPlusTimes with the weights compiled into the kernel (value
+    specialization) against the same DIRECT kernel reading them at run time
+    (same tiles, order 1) and against the library default, DGZ, FP64,
+    Z=32768 G=32 D=96 NM=16.  Weights: the dense matrices of the main workload;
+    the same with every other direction's coefficients zero (moments of half
+    the directions); one-hot (each moment takes one direction).  value = GB/s of
+    the dense value-specialized LTimes (algorithmic bytes / median time)."""
+    import numpy as np
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+    from sj_inputs import device as gdev
+
+    Z, G, D, NM = a.Z, a.G, a.D, a.NM
+    lay = "DGZ"
+    stream = torch.cuda.current_stream()
+    cols = G * Z
+    psi = torch.empty(D * cols, dtype=torch.float64, device="cuda")
+    gdev.fill(psi, 0, gen.ARR_PSI, gdev.DIST_U01, LAYOUTS.index(lay), (D, G, Z))
+    phi_in = torch.empty(NM * cols, dtype=torch.float64, device="cuda")
+    gdev.fill(phi_in, 0, gen.ARR_PHI, gdev.DIST_SYM)
+    phi = torch.empty(NM * cols, dtype=torch.float64, device="cuda")
+    out = torch.empty(D * cols, dtype=torch.float64, device="cuda")
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    Lp = gen.matrix_sym(0, gen.ARR_LPLUS, D, NM)
+    half_L, half_Lp = L.copy(), Lp.copy()
+    half_L[:, 1::2] = 0.0
+    half_Lp[1::2, :] = 0.0
+    pick = (np.arange(NM) * D) // NM
+    oh_L = np.zeros((NM, D))
+    oh_L[np.arange(NM), pick] = 1.0
+    cases = {"dense": (L, Lp), "half_directions": (half_L, half_Lp), "onehot": (oh_L, oh_L.T.copy())}
+    full = algorithmic_bytes(Z, G, D, NM)
+    res = {}
+    for name, (Lw, Lpw) in cases.items():
+        L_d, Lp_d = torch.from_numpy(Lw.ravel().copy()).cuda(), torch.from_numpy(Lpw.ravel().copy()).cuda()
+        for kern, W, W_d, x, y, kname in ((P.SJ_LTIMES, Lw, L_d, psi, phi, "ltimes"),
+                                          (P.SJ_LPLUSTIMES, Lpw, Lp_d, phi_in, out, "lplustimes")):
+            spec = dict(layout=lay, Z=Z, G=G, D=D, NM=NM)
+            hv = P.sj_specialize_values(kern, W, **spec)
+            hp = P.sj_specialize(kern, variant=P.SJ_VAR_DIRECT, order=1, **spec)
+            hd = P.sj_specialize(kern, **spec)
+            tv, _ = time_launches(lambda: P.sj_run(hv, [W_d, x, y]), a.steps, stream)
+            yv = y.clone()
+            tp, _ = time_launches(lambda: P.sj_run(hp, [W_d, x, y]), a.steps, stream)
+            same = bool(torch.equal(yv, y))
+            td, _ = time_launches(lambda: P.sj_run(hd, [W_d, x, y]), a.steps, stream)
+            # rows of the streamed input some nonzero coefficient reaches
+            needed_rows = int(np.count_nonzero(np.any(W != 0.0, axis=0)))   # columns of W = input rows
+            in_rows = D if kern == P.SJ_LTIMES else NM
+            out_rows = NM if kern == P.SJ_LTIMES else D
+            need = (needed_rows + out_rows) * cols * 8 + NM * D * 8
+            info = P.sj_handle_info(hv)
+            res[f"{kname}_{name}"] = dict(
+                values_us=round(tv * 1e3, 1), runtime_weights_us=round(tp * 1e3, 1), default_us=round(td * 1e3, 1),
+                speedup_vs_runtime_weights=round(tp / tv, 3), speedup_vs_default=round(td / tv, 3),
+                gbs_full_problem=round(full / (tv * 1e-3) / 1e9, 1), rows_read=needed_rows, rows_total=in_rows,
+                gbs_rows_read=round(need / (tv * 1e-3) / 1e9, 1), bitwise_equal_to_runtime_weights=same,
+                kernel=info["kernel_name"], compile_ms=round(info["compile_ms"], 1), code_bytes=info["code_bytes"],
+                vgprs=info["vgprs"])
+    dense = res["ltimes_dense"]
+    line = {
+        "metric": "LTimes/LPlusTimes with the weights compiled in (value specialization): GB/s and speedup over run-time weights",
+        "value": dense["gbs_full_problem"], "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": 0,
+        "ms_per_step": round(dense["values_us"] / 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64, seed 0)",
+        "config": {"workload": f"LTimes and LPlusTimes, DGZ, FP64, Z={Z} G={G} D={D} NM={NM}, weights as constants",
+                   "weights": list(cases)},
+        "roofline": {"bound": "hbm", "achieved": dense["gbs_full_problem"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dense["gbs_full_problem"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": dense["kernel"], "avg_us": dense["values_us"], "bytes_per_launch": full},
+        "cases": res,
     }
     print(json.dumps(line), flush=True)
 

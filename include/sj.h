@@ -197,6 +197,27 @@ sj_status sj_layout_from_string(const char *name, int32_t *out);
  * recompiles), SJ_ERR_LOAD, SJ_ERR_NOT_INITIALIZED. */
 sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out);
 
+/* Specialization on values (constant matrix elements, named as future work in
+ * ClangJIT section 6): like sj_specialize for SJ_LTIMES / SJ_LPLUSTIMES in FP64
+ * with the DIRECT structure, with the weight matrix's values compiled into the
+ * kernel.  `weights` is host memory holding the matrix the kernel would read
+ * (L row-major [NM][D] for LTimes, L+ row-major [D][NM] for LPlusTimes),
+ * `count` = NM * D doubles, all finite; it is read during the call only (the
+ * caller keeps ownership).  Every coefficient becomes a constant of the
+ * generated code and the reduction is fully unrolled; a term whose coefficient
+ * is +0 or -0 is not generated, so an input row that only zero coefficients
+ * reach is never read (a NaN or Inf in such a row no longer propagates).  The
+ * key holds two independent 64-bit hashes of the values' bit patterns: equal
+ * values return the same handle.  spec->variant must be AUTO or DIRECT and
+ * spec->order 0 or 1 (the run-time row rotation of order 2 would make the
+ * coefficients' positions unknown at compile time).  sj_run takes the plain
+ * kernel's pointers; the weight pointer is checked like the others but not
+ * read.  Errors: SJ_ERR_INVALID_ARG (null weights, count != NM * D, a
+ * non-finite value, order 2), SJ_ERR_UNSUPPORTED (another kernel, structure
+ * or dtype; D * NM * tile_n > 8192 products per thread). */
+sj_status sj_specialize_values(sj_kernel k, const sj_spec *spec, const double *weights, size_t count,
+                               sj_handle *out);
+
 /* Like sj_specialize, but on a miss the handle is built from `code` instead of
  * being compiled: `code`/`size` must be the code object that sj_handle_code
  * returned for a SJ_FLAG_COMPILE_ONLY specialization of the same spec, made by

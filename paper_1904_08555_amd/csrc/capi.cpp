@@ -164,7 +164,8 @@ sj_status ensure_device(int *device, const char **arch)
     return SJ_OK;
 }
 
-static sj_status build_handle(const SpecKey &key, const std::vector<char> *precompiled, sj_handle_ **out)
+static sj_status build_handle(const SpecKey &key, const std::vector<char> *precompiled, const double *values,
+                              sj_handle_ **out)
 {
     auto h = std::make_unique<sj_handle_>();
     h->key = key;
@@ -173,7 +174,7 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
     h->info.struct_size = sizeof(sj_kernel_info);
     auto t0 = std::chrono::steady_clock::now();
     std::string src;
-    sj_status s = emit_source(key, &src, &h->kernel_name, &h->kernel_name2);
+    sj_status s = emit_source(key, &src, &h->kernel_name, &h->kernel_name2, values);
     if (s != SJ_OK) return s;
     h->info.emit_ms = ms_since(t0);
 
@@ -251,7 +252,8 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
     return SJ_OK;
 }
 
-sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<char> *precompiled = nullptr)
+sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<char> *precompiled = nullptr,
+                       const double *values = nullptr)
 {
     g_lookups.fetch_add(1, std::memory_order_relaxed);
     {   // hit: shared lock only
@@ -290,7 +292,7 @@ sj_status get_or_build(const SpecKey &key, sj_handle_ **out, const std::vector<c
     lk.unlock();
 
     sj_handle_ *h = nullptr;
-    sj_status s = build_handle(key, precompiled, &h);
+    sj_status s = build_handle(key, precompiled, values, &h);
     std::string msg = (s == SJ_OK) ? std::string() : std::string(sj_last_error());
 
     lk.lock();
@@ -424,6 +426,35 @@ sj_status sj_specialize(sj_kernel k, const sj_spec *spec, sj_handle *out)
     if (s != SJ_OK) return s;
     if (f.map.size() >= 4096) f.map.clear();   // bounded: a thread cycling through many keys
     f.map.emplace(rk, h);
+    *out = h;
+    return SJ_OK;
+}
+
+sj_status sj_specialize_values(sj_kernel k, const sj_spec *spec, const double *weights, size_t count, sj_handle *out)
+{
+    clear_error();
+    if (!spec || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output handle");
+    if (spec->struct_size != sizeof(sj_spec)) return fail(SJ_ERR_INVALID_ARG, "sj_spec.struct_size mismatch");
+    if (spec->variant != SJ_VAR_AUTO && spec->variant != SJ_VAR_DIRECT)
+        return fail(SJ_ERR_UNSUPPORTED, "value specialization has the DIRECT structure only");
+    if (spec->order == 2) return fail(SJ_ERR_INVALID_ARG, "value specialization needs order 1 (no run-time row rotation)");
+    int device = -1;
+    const char *arch = "gfx950";
+    if (!(spec->flags & SJ_FLAG_COMPILE_ONLY)) {
+        sj_status s = ensure_device(&device, &arch);
+        if (s != SJ_OK) return s;
+    }
+    sj_spec t = *spec;
+    t.variant = SJ_VAR_DIRECT;
+    t.order = 1;
+    SpecKey key;
+    sj_status s = make_key(k, &t, device, arch, &key);
+    if (s != SJ_OK) return s;
+    s = make_values_key(weights, count, &key);
+    if (s != SJ_OK) return s;
+    sj_handle_ *h = nullptr;
+    s = get_or_build(key, &h, nullptr, weights);
+    if (s != SJ_OK) return s;
     *out = h;
     return SJ_OK;
 }

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <sstream>
@@ -75,6 +76,39 @@ uint64_t hash_words(const void *p, size_t bytes)
         a = ((a ^ w0) * 0x9E3779B97F4A7C15ull);
     }
     return mix64(a ^ ((b << 17) | (b >> 47)) ^ (uint64_t)bytes);
+}
+
+// FNV-1a over the bytes of 64-bit words, then a final avalanche: a hash
+// independent of hash_words' multiply-rotate chains (both name a value set).
+static uint64_t hash_fnv(const void *p, size_t bytes)
+{
+    const unsigned char *c = (const unsigned char *)p;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    return h;
+}
+
+sj_status make_values_key(const double *values, size_t count, SpecKey *key)
+{
+    if (!values) return fail(SJ_ERR_INVALID_ARG, "null weights");
+    if (key->kernel != SJ_LTIMES && key->kernel != SJ_LPLUSTIMES)
+        return fail(SJ_ERR_UNSUPPORTED, "value specialization applies to LTimes and LPlusTimes");
+    if (key->dtype != SJ_F64 || key->variant != SJ_VAR_DIRECT)
+        return fail(SJ_ERR_UNSUPPORTED, "value specialization needs FP64 and the DIRECT structure");
+    if (count != (size_t)(key->NM * key->D)) return fail(SJ_ERR_INVALID_ARG, "weight count must be NM * D");
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(values[i])) return fail(SJ_ERR_INVALID_ARG, "weights must be finite");
+    // every coefficient must be a constant at its FMA: the whole reduction is unrolled
+    if (key->D * key->NM * key->tile_n > 8192)
+        return fail(SJ_ERR_UNSUPPORTED, "value specialization unrolls at most 8192 products per thread");
+    key->full_unroll = 1;
+    key->values = 1;
+    key->vhash[0] = hash_words(values, count * sizeof(double));
+    key->vhash[1] = hash_fnv(values, count * sizeof(double));
+    return SJ_OK;
 }
 
 uint64_t key_hash(const SpecKey &k)
@@ -511,8 +545,9 @@ static const char *kCommonPrologue =
 // The templates name their kernel through this macro.
 static const char *base_name_macro(const SpecKey &) { return "SJ_KERNEL_NAME"; }
 
-sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std::string *name2)
+sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std::string *name2, const double *values)
 {
+    if (k.values && !values) return fail(SJ_ERR_INVALID_ARG, "a value-specialized key needs its weights to emit");
     if (name2) name2->clear();
     std::ostringstream o;
     const char *body = nullptr;
@@ -550,6 +585,17 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             } else {
                 body = (k.kernel == SJ_LTIMES) ? kTpl_ltimes_direct : kTpl_lplustimes_direct;
                 *name = (k.kernel == SJ_LTIMES) ? "sj_ltimes_direct" : "sj_lplustimes_direct";
+                if (k.values) {
+                    // the weights as exact hexadecimal literals, row-major like the run-time matrix
+                    *name += "_values";
+                    o << "#define SJ_WVAL 1\nstatic __device__ constexpr double sj_wv[" << k.NM * k.D << "] = {";
+                    char buf[40];
+                    for (int64_t i = 0; i < k.NM * k.D; ++i) {
+                        std::snprintf(buf, sizeof buf, "%a", values[i]);
+                        o << (i % 8 == 0 ? "\n    " : " ") << buf << ",";
+                    }
+                    o << "\n};\n";
+                }
             }
         } else if (k.variant == SJ_VAR_STAGED) {
             o << "#define SJ_TILE_N " << k.tile_n << "\n#define SJ_TILE_K " << k.tile_k << "\n";

@@ -26,6 +26,8 @@ struct SpecKey {
     int32_t device;          // -1 for compile-only keys
     int32_t lib_version;
     char arch[64];
+    int32_t values, pad1;    // 1: the weights' values are constants of the specialization
+    uint64_t vhash[2];       // two independent 64-bit hashes of those values (bit patterns)
 };
 
 bool key_equal(const SpecKey &a, const SpecKey &b);
@@ -49,7 +51,11 @@ sj_status make_key(sj_kernel k, const sj_spec *spec, int device, const char *arc
 
 // Source text (prologue + embedded template) and the kernel's symbol name.
 sj_status emit_source(const SpecKey &key, std::string *src, std::string *kernel_name,
-                      std::string *kernel_name2 = nullptr);
+                      std::string *kernel_name2 = nullptr, const double *values = nullptr);
+
+// Turn `key` (from make_key) into a value-specialized key for the `count`
+// weights at `values` (host): checks, forced tiles, content hashes.
+sj_status make_values_key(const double *values, size_t count, SpecKey *key);
 
 // Number of parameters of the cost-model MLP with `inputs` features and width `width`.
 inline int64_t mlp_nparams(int64_t inputs, int64_t width) { return width * inputs + width * width + 3 * width + 1; }

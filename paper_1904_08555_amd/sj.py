@@ -59,7 +59,7 @@ SJ_FLAG_ACCUMULATE = 0x40
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 
 EXPORTED = (
-    "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",
+    "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_values", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",
     "sj_batch_run", "sj_batch_graph_capture", "sj_batch_graph_launch", "sj_batch_plan_arrays", "sj_plan_destroy",
     "sj_run_adam", "sj_time_run", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
     "sj_last_error", "sj_status_string",
@@ -130,6 +130,7 @@ def lib() -> ctypes.CDLL:
         "sj_layout_from_string": [ctypes.c_char_p, P(i32)],
         "sj_specialize": [ctypes.c_int, P(sj_spec), P(vp)],
         "sj_specialize_with_code": [ctypes.c_int, P(sj_spec), ctypes.c_char_p, ctypes.c_size_t, P(vp)],
+        "sj_specialize_values": [ctypes.c_int, P(sj_spec), P(d), ctypes.c_size_t, P(vp)],
         "sj_run": [vp, P(vp), ctypes.c_int, vp],
         "sj_generic_run": [ctypes.c_int, P(sj_spec), P(vp), ctypes.c_int, vp],
         "sj_batch_plan": [vp, vp, i64, P(vp)],
@@ -250,6 +251,19 @@ def sj_specialize(kernel: int, spec: sj_spec | None = None, **kw) -> Handle:
         spec = make_spec(**kw)
     out = ctypes.c_void_p()
     _check(lib().sj_specialize(int(kernel), ctypes.byref(spec), ctypes.byref(out)))
+    return Handle(out.value, int(kernel))
+
+
+def sj_specialize_values(kernel: int, weights, spec: sj_spec | None = None, **kw) -> Handle:
+    """Value specialization: `weights` (the L or L+ matrix the kernel would read, host,
+    any array-like of NM * D floats) compiled into the kernel as constants."""
+    import numpy as np
+    if spec is None:
+        spec = make_spec(**kw)
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    out = ctypes.c_void_p()
+    _check(lib().sj_specialize_values(int(kernel), ctypes.byref(spec), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      w.size, ctypes.byref(out)))
     return Handle(out.value, int(kernel))
 
 

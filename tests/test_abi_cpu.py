@@ -327,3 +327,38 @@ def test_fused_structures(P):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_LTIMES_LPLUS, **spec)
         assert e.value.status == status, bad
+
+
+def test_values_specs(P):
+    """Value specialization: argument checks, the weights as exact literals in
+    the emitted code, one compile per distinct value set."""
+    import numpy as np
+    co = P.SJ_FLAG_COMPILE_ONLY
+    base = dict(layout="DGZ", Z=64, G=2, D=8, NM=4, flags=co)
+    L = np.arange(32, dtype=np.float64) / 3.0
+    s0 = P.sj_stats()
+    h1 = P.sj_specialize_values(P.SJ_LTIMES, L, **base)
+    h2 = P.sj_specialize_values(P.SJ_LTIMES, L.copy(), **base)
+    assert h1 == h2
+    assert P.sj_stats()["compiles"] - s0["compiles"] == 1
+    assert P.sj_handle_info(h1)["kernel_name"] == "sj_ltimes_direct_values_dgz"
+    onehot = np.zeros((4, 8))
+    onehot[np.arange(4), [0, 2, 4, 6]] = 1.0
+    h3 = P.sj_specialize_values(P.SJ_LTIMES, onehot, **base)
+    assert h3 != h1 and P.sj_handle_info(h3)["code_bytes"] < P.sj_handle_info(h1)["code_bytes"]
+    bad = [
+        (dict(weights=L[:31]), P.SJ_ERR_INVALID_ARG),
+        (dict(weights=np.where(np.arange(32) == 3, np.inf, L)), P.SJ_ERR_INVALID_ARG),
+        (dict(weights=L, order=2), P.SJ_ERR_INVALID_ARG),
+        (dict(weights=L, variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED),
+        (dict(weights=L, kernel=P.SJ_LTIMES_LPLUS), P.SJ_ERR_UNSUPPORTED),
+        (dict(weights=np.zeros(4096 * 4), D=4096), P.SJ_ERR_UNSUPPORTED),
+    ]
+    for b, status in bad:
+        b = dict(b)
+        kern = b.pop("kernel", P.SJ_LTIMES)
+        w = b.pop("weights")
+        spec = dict(base, **b)
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize_values(kern, w, **spec)
+        assert e.value.status == status, b
