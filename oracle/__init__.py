@@ -50,6 +50,8 @@ def lib():
             f.argtypes = [i32, i64, i64, i64, i64, vp, vp, vp]
             f.restype = i32
         L.orc_bgemm.argtypes = [i64, vp, vp, vp, vp, vp]
+        for f in (L.orc_scattering, L.orc_scattering_absscale):
+            f.argtypes = [i32, i64, i64, i64, i64, vp, vp, vp, vp]
         L.orc_bgemm.restype = i32
         L.orc_bf16_round.argtypes = [d]
         L.orc_bf16_round.restype = d
@@ -114,6 +116,25 @@ def ltimes_absscale(layout, Z, G, D, NM, L, psi) -> np.ndarray:
     rc = lib().orc_ltimes_absscale(_layout_id(layout), Z, G, D, NM, _ptr(L), _ptr(psi), _ptr(out))
     if rc != 0:
         raise ValueError("orc_ltimes_absscale failed")
+    return out
+
+
+def scattering(layout, Z, G, NM, S, mat, phi, absolute=False) -> np.ndarray:
+    """phi_out (flat, ``layout`` order with D -> NM) = the scattering source of
+    phi: S is [nmat][n_max + 1][G][G], mat [Z] int32 material of each zone.
+    ``absolute`` returns the error scale sum |S| |phi| instead."""
+    S = _f64(S).reshape(-1)
+    phi = _f64(phi).reshape(-1)
+    mat = np.ascontiguousarray(np.asarray(mat, dtype=np.int32).reshape(-1))
+    import math
+    nl = math.isqrt(NM - 1) + 1          # degrees 0 .. floor(sqrt(NM - 1))
+    assert S.size % (nl * G * G) == 0 and phi.size == NM * G * Z and mat.size == Z
+    nmat = S.size // (nl * G * G)
+    out = np.empty(NM * G * Z, dtype=np.float64)
+    f = lib().orc_scattering_absscale if absolute else lib().orc_scattering
+    rc = f(_layout_id(layout), Z, G, NM, nmat, _ptr(S), mat.ctypes.data, _ptr(phi), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_scattering failed (%d)" % rc)
     return out
 
 

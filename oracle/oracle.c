@@ -21,6 +21,15 @@
  *    its Kripke layout-dispatch listing (section 5.2).  A nesting name gives the
  *    storage order of the three axes, rightmost fastest; phi uses the same order
  *    with D replaced by NM; L is row-major [NM][D], L+ row-major [D][NM].
+ *  - Scattering (a reading: the paper names Kripke's scattering kernel among
+ *    the de-multiversioned ones, section 5.2 footnote, but does not define it):
+ *    the standard within-group-to-group scattering source of discrete-ordinates
+ *    transport,
+ *        phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] * phi[nm,g',z]
+ *    where n(nm) = floor(sqrt(nm)) is the Legendre degree of moment nm (moments
+ *    ordered by degree, nm = n^2 + n + m), mat(z) the zone's material, and S
+ *    row-major [nmat][n_max + 1][G][G] (row g receives from column g').  phi
+ *    and phi_out use the moment arrays' storage order.
  *  - Batched small products: C_i = A_i * B_i, square, row-major, as in the
  *    paper's RAJA small matrix-multiply benchmark (section 5.1), one product per
  *    instance of a packed batch.
@@ -127,6 +136,55 @@ int orc_ltimes_absscale(int layout, int64_t Z, int64_t G, int64_t D, int64_t NM,
         }
     }
     return 0;
+}
+
+/* Legendre degree of moment nm: the largest n with n*n <= nm. */
+static int64_t orc_degree(int64_t nm)
+{
+    int64_t n = 0;
+    while ((n + 1) * (n + 1) <= nm) ++n;
+    return n;
+}
+
+/* phi_out[nm,g,z] = sum_{g' ascending} S[mat[z]][n(nm)][g][g'] * phi[nm,g',z];
+ * overwrites phi_out.  Returns 0, -1 for an unknown layout, -2 for a material
+ * index outside [0, nmat).  With `absolute` set it forms the error scale
+ * sum_g' |S[..][g][g']| |phi[nm,g',z]| instead. */
+static int orc_scatter_impl(int layout, int64_t Z, int64_t G, int64_t NM, int64_t nmat, const double *S,
+                            const int32_t *mat, const double *phi, double *out, int absolute)
+{
+    if (layout < 0 || layout > 5) return -1;
+    for (int64_t z = 0; z < Z; ++z)
+        if (mat[z] < 0 || mat[z] >= nmat) return -2;
+    const int64_t nl = orc_degree(NM - 1) + 1;
+    int64_t ncol = NM * Z;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < ncol; ++c) {
+        int64_t nm = c / Z, z = c % Z;
+        const double *Sm = S + ((int64_t)mat[z] * nl + orc_degree(nm)) * G * G;
+        for (int64_t g = 0; g < G; ++g) {
+            double acc = 0.0;
+            for (int64_t gp = 0; gp < G; ++gp) {
+                double x = phi[orc_index(layout, (size_t)nm, (size_t)gp, (size_t)z, (size_t)NM, (size_t)G, (size_t)Z)];
+                double prod = absolute ? fabs(Sm[g * G + gp]) * fabs(x) : Sm[g * G + gp] * x;
+                acc = acc + prod;
+            }
+            out[orc_index(layout, (size_t)nm, (size_t)g, (size_t)z, (size_t)NM, (size_t)G, (size_t)Z)] = acc;
+        }
+    }
+    return 0;
+}
+
+int orc_scattering(int layout, int64_t Z, int64_t G, int64_t NM, int64_t nmat, const double *S,
+                   const int32_t *mat, const double *phi, double *phi_out)
+{
+    return orc_scatter_impl(layout, Z, G, NM, nmat, S, mat, phi, phi_out, 0);
+}
+
+int orc_scattering_absscale(int layout, int64_t Z, int64_t G, int64_t NM, int64_t nmat, const double *S,
+                            const int32_t *mat, const double *phi, double *scale)
+{
+    return orc_scatter_impl(layout, Z, G, NM, nmat, S, mat, phi, scale, 1);
 }
 
 /* C_i = A_i * B_i for i < count; instance i is n[i] x n[i], row-major, stored at
