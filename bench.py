@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "gpurun_out/tuned_moments.json) instead of tuning")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values"),
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -119,6 +119,8 @@ def main():
         return bench_fused(a)
     if a.workload == "values":
         return bench_values(a)
+    if a.workload == "scattering":
+        return bench_scattering(a)
     return bench_moments(a)
 
 
@@ -664,6 +666,60 @@ def bench_values(a):
                      "frac": round(dense["gbs_full_problem"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": dense["kernel"], "avg_us": dense["values_us"], "bytes_per_launch": full},
         "cases": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_scattering(a):
+    """Scattering source phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] phi[nm,g',z]
+    over the six nestings, FP64, Z=32768 G=32 NM=16 (degrees 0..3), four
+    materials in contiguous zone regions; also every zone's material drawn at
+    random (per-lane matrices) for one nesting.  value = algorithmic bytes of
+    the six launches / their summed median times."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+    from sj_inputs import device as gdev
+
+    Z, G, NM, nmat = a.Z, a.G, a.NM, 4
+    layouts = [x for x in a.layouts.split(",") if x]
+    stream = torch.cuda.current_stream()
+    nl = math.isqrt(NM - 1) + 1
+    rng = np.random.default_rng(0)
+    S_d = torch.from_numpy(rng.uniform(0.0, 1.0 / G, (nmat, nl, G, G)).ravel()).cuda()
+    mat_reg = torch.from_numpy(((np.arange(Z) * nmat) // Z).astype(np.int32)).cuda()
+    mat_rnd = torch.from_numpy(rng.integers(0, nmat, Z).astype(np.int32)).cuda()
+    phi = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(phi)
+    nbytes = 2 * NM * G * Z * 8 + S_d.numel() * 8 + Z * 4
+    res, tot = {}, 0.0
+    for lay in layouts:
+        gdev.fill(phi, 0, gen.ARR_PHI, gdev.DIST_U01, LAYOUTS.index(lay), (NM, G, Z))
+        h = P.sj_specialize(P.SJ_SCATTERING, layout=lay, Z=Z, G=G, NM=NM, count=nmat)
+        t, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_reg, phi, out]), a.steps, stream)
+        tr, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream)
+        info = P.sj_handle_info(h)
+        tot += t
+        res[lay] = dict(us=round(t * 1e3, 1), gbs=round(nbytes / (t * 1e-3) / 1e9, 1),
+                        frac=round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        random_materials_us=round(tr * 1e3, 1), kernel=info["kernel_name"], vgprs=info["vgprs"],
+                        compile_ms=round(info["compile_ms"], 1))
+    dom = max(res, key=lambda k: res[k]["us"])
+    line = {
+        "metric": "scattering source GB/s over six nestings (specialized kernels)",
+        "value": round(nbytes * len(layouts) / (tot * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": 0, "ms_per_step": round(tot, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64 phi, seeded S and materials)",
+        "config": {"workload": f"scattering, FP64, Z={Z} G={G} NM={NM}, {nmat} materials in zone regions",
+                   "layouts": layouts},
+        "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": res[dom]["frac"], "traffic": None, "kernel": res[dom]["kernel"],
+                     "avg_us": res[dom]["us"], "bytes_per_launch": nbytes},
+        "per_layout": res,
     }
     print(json.dumps(line), flush=True)
 

@@ -78,7 +78,8 @@ typedef enum sj_kernel {
     SJ_MLP_FWD = 4,
     SJ_MLP_BWD = 5,
     SJ_ADAM = 6,
-    SJ_LTIMES_LPLUS = 7    /* LTimes then LPlusTimes on the same columns in one pass (phi stays on chip) */
+    SJ_LTIMES_LPLUS = 7,   /* LTimes then LPlusTimes on the same columns in one pass (phi stays on chip) */
+    SJ_SCATTERING = 8      /* scattering source phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] phi[nm,g',z] */
 } sj_kernel;
 
 /* Storage order of a psi-like array's three axes, rightmost fastest.  phi uses
@@ -133,7 +134,7 @@ typedef struct sj_spec {
     int32_t  layout;        /* sj_layout (LTimes / LPlusTimes) */
     int32_t  variant;       /* sj_variant */
     int64_t  Z, G, D, NM;   /* LTimes / LPlusTimes: zones, groups, directions, moments; each in [1, 2^31-1] */
-    int64_t  count;         /* BGEMM generic path: number of instances */
+    int64_t  count;         /* BGEMM generic path: number of instances; SJ_SCATTERING: number of materials */
     uint32_t class_mask;    /* BGEMM: bit n set when size class n (1 <= n <= 16) occurs; 0 = all of 1..16 */
     int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
                                FP64 MFMA rows: 16-row tiles per wave (1..8); FP64 MFMA columns and
@@ -235,6 +236,11 @@ sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *
  *                  phi [NM*G*Z] appended when the moments are wanted too (all f64); psi_out =
  *                  L+ (L psi) with the moments kept on chip (FP64; DIRECT structure, or
  *                  the matrix-core row structure when D is innermost)
+ *   SJ_SCATTERING: {S [count*(n_max+1)*G*G] f64, mat [Z] int32, phi [NM*G*Z] f64, phi_out [NM*G*Z] f64}
+ *                  with n_max = floor(sqrt(NM - 1)); S row-major [material][degree][g][g'] (row g receives
+ *                  from group g'); phi and phi_out in the spec's nesting with D read as NM; the degree of
+ *                  moment nm is floor(sqrt(nm)).  A zone whose material is outside [0, count) gets NaN
+ *                  outputs (nothing is read out of range).  Overwrites phi_out.
  *   SJ_MLP_FWD:    {theta f32, X [rows*inputs] f32, y [rows] f32}
  *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32,
  *                  workspace [rows*(4*width+2)] f32}

@@ -530,6 +530,22 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
         if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
         return SJ_OK;
     }
+    if (k.kernel == SJ_SCATTERING) {
+        // {S, mat, phi, phi_out}
+        size_t nl = 0;
+        while ((nl + 1) * (nl + 1) <= (size_t)k.NM - 1) ++nl;
+        nl += 1;
+        const size_t line = (size_t)k.NM * (size_t)k.G * (size_t)k.Z * 8;
+        const size_t bytes[4] = {(size_t)k.rows * nl * (size_t)k.G * (size_t)k.G * 8, (size_t)k.Z * 4, line, line};
+        sj_status s = check_ptrs(ptrs, nptrs, 4, bytes, 3);
+        if (s != SJ_OK) return s;
+        void *a0 = ptrs[0], *a1 = ptrs[1], *a2 = ptrs[2], *a3 = ptrs[3];
+        void *args[] = {&a0, &a1, &a2, &a3};
+        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0,
+                                             (hipStream_t)stream, args, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD) {
         const size_t R = (size_t)k.rows, F = (size_t)k.inputs, H = (size_t)k.width;
         const size_t P = (size_t)mlp_nparams(k.inputs, k.width);

@@ -424,6 +424,37 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         (void)outn;
         return (*out = key), SJ_OK;
     }
+    if (k == SJ_SCATTERING) {
+        // scattering source over the six nestings of the moment arrays: one thread per (nm, z) line
+        if (s->dtype != SJ_F64) return fail(SJ_ERR_INVALID_ARG, "scattering is FP64 (dtype SJ_F64)");
+        if (s->layout < SJ_DGZ || s->layout > SJ_ZGD) return fail(SJ_ERR_INVALID_ARG, "layout out of range");
+        const int64_t dims[3] = {s->Z, s->G, s->NM};
+        for (int64_t v : dims)
+            if (v < 1 || v > kMaxDim) return fail(SJ_ERR_INVALID_ARG, "sizes must be in [1, 2^31-1]");
+        if (s->count < 1 || s->count > 65536) return fail(SJ_ERR_INVALID_ARG, "count (materials) must be in [1, 65536]");
+        if (s->NM > 4096) return fail(SJ_ERR_UNSUPPORTED, "NM is limited to 4096");
+        if (s->G > 64) return fail(SJ_ERR_UNSUPPORTED, "scattering keeps a line's G values in registers: G <= 64");
+        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
+            return fail(SJ_ERR_UNSUPPORTED, "scattering has the DIRECT structure only");
+        if (s->tile_n != 0 || s->tile_k != 0 || s->unroll != 0 || (s->order != 0 && s->order != 1))
+            return fail(SJ_ERR_INVALID_ARG, "scattering takes no tiles");
+        if (s->flags & SJ_FLAG_ACCUMULATE) return fail(SJ_ERR_INVALID_ARG, "scattering overwrites its output");
+        const int64_t lines = s->NM * s->Z;
+        if (lines > (int64_t(1) << 40) || s->G * lines > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "array size overflows");
+        int64_t nl = 0;
+        while ((nl + 1) * (nl + 1) <= s->NM - 1) ++nl;
+        nl += 1;
+        if (s->count * nl * s->G * s->G > (int64_t(1) << 40)) return fail(SJ_ERR_INVALID_ARG, "S too large");
+        key.layout = s->layout;
+        key.Z = s->Z; key.G = s->G; key.NM = s->NM;
+        key.rows = s->count;   // materials
+        key.variant = SJ_VAR_DIRECT;
+        key.block = s->block ? s->block : 256;
+        if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+        key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+        key.order = 1;
+        return (*out = key), SJ_OK;
+    }
     if (k == SJ_MLP_FWD || k == SJ_MLP_BWD || k == SJ_ADAM) {
         if (s->dtype != SJ_F32) return fail(SJ_ERR_INVALID_ARG, "the MLP kernels are FP32 (dtype SJ_F32)");
         if (s->rows < 1 || s->rows > (int64_t(1) << 24)) return fail(SJ_ERR_INVALID_ARG, "rows must be in [1, 2^24]");
@@ -487,6 +518,7 @@ Geometry key_geometry(const SpecKey &k)
     Geometry g{0, (unsigned)k.block, 0};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
+    if (k.kernel == SJ_SCATTERING) g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         if (k.variant == SJ_VAR_DIRECT) {
             const int64_t nv = k.B * (k.I / k.tile_n);
@@ -628,6 +660,34 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n";
             body = (k.tile_n == 4) ? kTpl_ltimes_bf16w : kTpl_ltimes_bf16;
         }
+    }
+    if (k.kernel == SJ_SCATTERING) {
+        // strides of the (nm, g, z) axes in the nesting, rightmost fastest
+        const int64_t NM = k.NM, G = k.G, Z = k.Z;
+        int64_t snm = 0, sg = 0, sz = 0;
+        switch (k.layout) {
+        case SJ_DGZ: snm = G * Z; sg = Z; sz = 1; break;
+        case SJ_DZG: snm = Z * G; sz = G; sg = 1; break;
+        case SJ_GDZ: sg = NM * Z; snm = Z; sz = 1; break;
+        case SJ_GZD: sg = Z * NM; sz = NM; snm = 1; break;
+        case SJ_ZDG: sz = NM * G; snm = G; sg = 1; break;
+        default: /* ZGD */ sz = G * NM; sg = NM; snm = 1; break;
+        }
+        int64_t nl = 0;
+        while ((nl + 1) * (nl + 1) <= NM - 1) ++nl;
+        nl += 1;
+        int ntl = 1, nts = 1;   // phi is read once and phi_out written once: streamed
+        if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
+        if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
+        o << "#define SJ_NM " << NM << "\n#define SJ_G " << G << "\n#define SJ_Z " << Z << sfx << "\n#define SJ_NMAT "
+          << k.rows << "\n#define SJ_NL " << nl << "\n#define SJ_SNM " << snm << sfx << "\n#define SJ_SG " << sg << sfx
+          << "\n#define SJ_SZ " << sz << sfx << "\n#define SJ_LANE_NM " << (snm < sz ? 1 : 0) << "\n#define SJ_SLDS "
+          << (nl * (G * G + 2) * 8 <= 64 * 1024 ? 1 : 0) << "\n#define SJ_BLOCK "
+          << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n";
+        body = kTpl_scattering_direct;
+        static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
+        *name = std::string("sj_scattering_direct_") + lay[k.layout];
+        o << "#define SJ_KERNEL_NAME " << *name << "\n";
     }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {
         o << "#define SJ_R " << k.rows << "\n#define SJ_F " << (k.inputs ? k.inputs : 1) << "\n#define SJ_H "

@@ -35,6 +35,7 @@ SJ_MLP_FWD = 4
 SJ_MLP_BWD = 5
 SJ_ADAM = 6
 SJ_LTIMES_LPLUS = 7
+SJ_SCATTERING = 8
 # sj_layout
 LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 SJ_DGZ, SJ_DZG, SJ_GDZ, SJ_GZD, SJ_ZDG, SJ_ZGD = range(6)

@@ -362,3 +362,21 @@ def test_values_specs(P):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize_values(kern, w, **spec)
         assert e.value.status == status, b
+
+
+def test_scattering_specs(P):
+    co = P.SJ_FLAG_COMPILE_ONLY
+    base = dict(layout="ZGD", Z=40, G=6, NM=9, count=2, flags=co)
+    h = P.sj_specialize(P.SJ_SCATTERING, **base)
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_scattering_direct_zgd"
+    assert h != P.sj_specialize(P.SJ_SCATTERING, **dict(base, count=3))   # the material count is part of the key
+    src = P.sj_emit_source(P.SJ_SCATTERING, **base)
+    assert "#define SJ_NL 3" in src and "#define SJ_LANE_NM 1" in src and "#define SJ_SG 9" in src
+    assert "#define SJ_LANE_NM 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(base, layout="DGZ"))
+    for bad, status in ((dict(count=0), P.SJ_ERR_INVALID_ARG), (dict(G=65), P.SJ_ERR_UNSUPPORTED),
+                        (dict(variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED), (dict(tile_n=2), P.SJ_ERR_INVALID_ARG),
+                        (dict(flags=co | P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG), (dict(dtype=P.SJ_BF16), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout=7), P.SJ_ERR_INVALID_ARG)):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_SCATTERING, **dict(base, **bad))
+        assert e.value.status == status, bad
