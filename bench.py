@@ -40,15 +40,24 @@ LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 # were taken on: a kernel whose source has changed since reports traffic null.  The summaries with the
 # commands are the *_hbm_counters.md and bgemm_*_counters.md files under profiles/.
 MEASURED_TRAFFIC = {
-    # LTimes ZGD, Z=32768 G=32 D=96 NM=16, FP64 MFMA rows, tile_n 2, block 256, ordinary loads
-    "43a31569646b5a5603f8824a8fa578f85da6b09d": (393305 * 2 + 131072) * 1024,
-    # LPlusTimes ZGD, same shape, MFMA rows, tile_n 2, block 512, nontemporal
-    "17895bfb76d06a63c9b3cbcc4231444398228b5f": (66606 * 2 + 786621) * 1024,
-    # LTimes / LPlusTimes DGZ, same shape, FP64 MFMA columns, tile_n 2, unroll 8
-    "adcaa487244ce6230680886385d1d35cfd2a96b2": (393303 * 2 + 131072) * 1024,
-    "2ca0cf222c7d6d4c16fd12d643f88e422a9e712b": (65626 * 2 + 786709) * 1024,
-    # batched products, 200,000 instances, default specialization
-    "137a01fa3f26d08483c506090e188ed1e385e877": (172659 * 2 + 176083) * 1024,
+    # HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB device copy),
+    # keyed by the SHA-1 of the emitted source the counters were taken on.
+    # Z=32768 G=32 D=96 NM=16, the tuned specializations of the six nestings:
+    "a6f46348492bcdfd72c5cefed2cefafd23102547": 939814010,  # sj_ltimes_direct_dgz
+    "89c58e2ebb508b12336bcd6a790b761a37a875b2": 940363515,  # sj_lplustimes_cols_mfma_dgz
+    "b6d6da413a756dc954db8fcbf4f586e239342041": 939779834,  # sj_ltimes_direct_dzg
+    "2fce2b3e613e8628a020b669659b960ac7a3d9ba": 940332283,  # sj_lplustimes_cols_mfma_dzg
+    "858625ac709482476393c2c4337e7ac79257878f": 940025525,  # sj_ltimes_direct_gdz
+    "eabf1e426515efd23bb94fd27967cb38947ab96f": 940663867,  # sj_lplustimes_cols_mfma_gdz
+    "e2f4680432ca699cac6a3dd564cd98b9423f75ae": 939710460,  # sj_ltimes_rows_mfma_lds_gzd
+    "7d0562e5aabb0386599d1ba19780c26f9cab0b4d": 939746045,  # sj_lplustimes_rows_mfma_gzd
+    "f303a0f1a4664f56e737754a87e151907e3b93a9": 939772987,  # sj_ltimes_direct_zdg
+    "198e190815ed8b22063d73fb3f6a1ca016170b7d": 940265275,  # sj_lplustimes_cols_mfma_zdg
+    "385b9213b1c196f5763daab7b57762938b92611d": 939708156,  # sj_ltimes_rows_mfma_lds_zgd
+    "c524a2bbfc0f9a1e5e68eb37e59b080356775bee": 939764733,  # sj_lplustimes_rows_mfma_zgd
+    "456ff6bccbb93f1b5b963602531428289040ee2d": 940383099,  # sj_lplustimes_cols_mfma_zdg (unroll 2)
+    # batched products, 200,000 instances n ~ U{3..16}, default specialization:
+    "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
 
 
