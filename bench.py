@@ -334,8 +334,16 @@ def bench_moments(a):
     kern = {}
     for key in order:
         ms = statistics.median(per_kernel[key])
-        kern[f"{key[1]}_{key[0]}"] = dict(us=round(ms * 1e3, 2), gbs=round(nbytes / (ms * 1e-3) / 1e9, 1),
+        sd = statistics.stdev(per_kernel[key]) if len(per_kernel[key]) > 1 else 0.0
+        kern[f"{key[1]}_{key[0]}"] = dict(us=round(ms * 1e3, 2), std_us=round(sd * 1e3, 2),
+                                           gbs=round(nbytes / (ms * 1e-3) / 1e9, 1),
                                            frac=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    # the measured device-copy rate (1 GiB read + 1 GiB written), the practical ceiling beside the nominal peak
+    csrc = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    cdst = torch.empty_like(csrc)
+    cmed, _ = time_launches(lambda: cdst.copy_(csrc), 10, torch.cuda.current_stream())
+    copy_gbs = 2 * (1 << 30) / (cmed * 1e-3) / 1e9
+    del csrc, cdst
     # the same step with the default (untuned) specializations (skipped when the
     # tuned choices come from a file, as in a profiled run)
     default_value = None
@@ -400,6 +408,28 @@ def bench_moments(a):
         cpu = dict(value=round(done_bytes / spent / 1e9, 3), unit="GB/s", cores=threads, kind="oracle",
                    sample=f"{lay_i} zone slabs of {zs} zones x G={G} (D={D}, NM={NM}), LTimes + LPlusTimes, "
                           f"nestings cycled {','.join(layouts)}; {spent:.1f} s of oracle time")
+        # the same oracle on one thread, a few slabs (about 3 s)
+        oracle.set_threads(1)
+        b1, s1, k = 0, 0.0, 0
+        while s1 < min(3.0, a.cpu_seconds) and k < 500:
+            lay = layouts[k % len(layouts)]
+            cols = gen.psi_columns(0, D, G, Z, np.repeat(np.arange(G), zs), np.tile(np.arange(zs), G))
+            psi = gen.to_layout(cols.reshape(D, G, zs), lay)
+            t0 = time.perf_counter()
+            phi = oracle.ltimes(lay, zs, G, D, NM, L, psi)
+            oracle.lplustimes(lay, zs, G, D, NM, Lp, phi)
+            s1 += time.perf_counter() - t0
+            b1 += 2 * algorithmic_bytes(zs, G, D, NM)
+            k += 1
+        oracle.set_threads(threads)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        cpu.update(single_thread_value=round(b1 / s1 / 1e9, 3), single_thread_sample=f"{k} slabs, {s1:.1f} s",
+                   host_cpu=model, host_logical_cpus=os.cpu_count())
 
     line = {
         "metric": METRIC,
@@ -421,7 +451,9 @@ def bench_moments(a):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, *specs[dom]),
                      "kernel": f"{dom[1]}_{dom[0]}", "avg_us": round(dom_ms * 1e3, 2),
-                     "bytes_per_launch": nbytes},
+                     "bytes_per_launch": nbytes, "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+        "step_frac_of_measured_copy": round(value / copy_gbs, 4),
         "cpu_baseline": cpu,
         "kernels": kern,
         "generic": generic,
