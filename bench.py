@@ -93,9 +93,11 @@ def parse():
     ap.add_argument("--tile", default="", help="override tile params, e.g. 'tile_n=2,unroll=8,block=256'")
     ap.add_argument("--no-tune", action="store_true",
                     help="moments: time the default specializations only (no exhaustive tuning first)")
+    ap.add_argument("--out-dir", default="bench_out",
+                    help="directory for the tuning results (tuned_moments.json) and the picker's data")
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
-                         "gpurun_out/tuned_moments.json) instead of tuning")
+                         "<out-dir>/tuned_moments.json) instead of tuning")
     ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
@@ -193,8 +195,8 @@ def bench_moments(a):
                     print(f"tuned {kname} {lay}: {r['best']} {r['best_ms'] * 1e3:.1f} us "
                           f"({len(r['results'])} candidates)", file=sys.stderr, flush=True)
         tune_s = time.perf_counter() - t0
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        with open(os.path.join(ROOT, "gpurun_out", "tuned_moments.json"), "w") as f:
+        os.makedirs(os.path.join(ROOT, a.out_dir), exist_ok=True)
+        with open(os.path.join(ROOT, a.out_dir, "tuned_moments.json"), "w") as f:
             json.dump({f"{k[1]}_{k[0]}": v for k, v in tuned.items()}, f)
     for lay in layouts:
         for kname, kid in (("ltimes", P.SJ_LTIMES), ("lplustimes", P.SJ_LPLUSTIMES)):
@@ -288,7 +290,7 @@ def bench_moments(a):
                         tuned[key] = c
                         refined += 1
                 specs[key] = best_spec
-        with open(os.path.join(ROOT, "gpurun_out", "tuned_moments.json"), "w") as f:
+        with open(os.path.join(ROOT, a.out_dir, "tuned_moments.json"), "w") as f:
             json.dump({f"{k[1]}_{k[0]}": v for k, v in tuned.items()}, f)
 
     # the specializations the timed steps use (after any refinement)
@@ -854,13 +856,13 @@ def bench_picker(a):
     from paper_1904_08555_amd import picker
 
     t0 = time.perf_counter()
-    os.makedirs("gpurun_out", exist_ok=True)
+    os.makedirs(a.out_dir, exist_ok=True)
     res, pk = picker.run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=12, epochs=200,
                                     log=lambda m: print(m, file=sys.stderr, flush=True),
-                                    dump="gpurun_out/picker_data.json")
+                                    dump=os.path.join(a.out_dir, "picker_data.json"))
     wall = time.perf_counter() - t0
-    os.makedirs("gpurun_out", exist_ok=True)
-    pk.save("gpurun_out/picker_weights.json")
+    os.makedirs(a.out_dir, exist_ok=True)
+    pk.save(os.path.join(a.out_dir, "picker_weights.json"))
     line = {
         "metric": "picker regret vs exhaustive autotuner (mean over held-out shapes)",
         "value": res["regret_mean"], "unit": "fraction", "n_gpus": 1, "steps": 1, "warmup": 0,

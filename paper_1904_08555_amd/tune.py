@@ -5,7 +5,7 @@ For a problem shape it enumerates a candidate set C(shape) of specializations
 threads (each sj_specialize call releases the interpreter lock while hiprtc
 runs), times each one with sj_time_run, and returns the fastest together with
 every timing.  This is the profile-guided autotuning named as future work in
-ClangJIT section 6; it is also the judge of the learned picker.
+ClangJIT section 6; it is also the reference the learned picker is measured against.
 
 The candidate set (at most 33 per kernel and layout):
   * innermost axis is a column axis (DGZ, DZG, GDZ, ZDG):
