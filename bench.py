@@ -370,21 +370,25 @@ def bench_moments(a):
             psi, phi, out = bufs[lay]
             for kname, kid, ptrs in (("ltimes", P.SJ_LTIMES, [L_d, psi, phi]),
                                      ("lplustimes", P.SJ_LPLUSTIMES, [Lp_d, phi, out])):
-                gs = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM)
-                for _ in range(2):
-                    P.sj_generic_run(kid, ptrs, gs)
-                ts = []
-                for _ in range(max(3, a.steps // 2)):
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    P.sj_generic_run(kid, ptrs, gs)
-                    e1.record(stream)
-                    ts.append((e0, e1))
-                torch.cuda.synchronize()
-                ms = statistics.median([x.elapsed_time(y) for x, y in ts])
-                jit_us = kern[f"{kname}_{lay}"]["us"]
-                generic[f"{kname}_{lay}"] = dict(us=round(ms * 1e3, 2), gbs=round(nbytes / (ms * 1e-3) / 1e9, 1),
-                                                 jit_speedup=round(ms * 1e3 / jit_us, 3))
+                res_g = {}
+                # one kernel for every nesting, and the kernel compiled for this nesting (sizes at run time)
+                for mode, fl in (("", 0), ("per_layout_", P.SJ_FLAG_GENERIC_PER_LAYOUT)):
+                    gs = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM, flags=fl)
+                    for _ in range(2):
+                        P.sj_generic_run(kid, ptrs, gs)
+                    ts = []
+                    for _ in range(max(3, a.steps // 2)):
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        P.sj_generic_run(kid, ptrs, gs)
+                        e1.record(stream)
+                        ts.append((e0, e1))
+                    torch.cuda.synchronize()
+                    ms = statistics.median([x.elapsed_time(y) for x, y in ts])
+                    jit_us = kern[f"{kname}_{lay}"]["us"]
+                    res_g.update({f"{mode}us": round(ms * 1e3, 2), f"{mode}gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                  f"{mode}jit_speedup": round(ms * 1e3 / jit_us, 3)})
+                generic[f"{kname}_{lay}"] = res_g
 
     # --- CPU oracle on a bounded sample of the same workload ------------------------------
     cpu = None

@@ -126,6 +126,9 @@ typedef enum sj_variant {
  * column kernels, ordinary loads for LPlusTimes and for the FP64 MFMA row
  * kernel.  The two flags of a pair exclude each other; every policy flag is
  * part of the specialization key. */
+#define SJ_FLAG_GENERIC_PER_LAYOUT 0x80u /* sj_generic_run, LTimes / LPlusTimes: the kernel compiled ahead of time
+                                           for the spec's nesting (sizes still run-time arguments), Kripke's
+                                           multiversioning; without it one kernel serves every nesting */
 #define SJ_FLAG_DEBUG_FAIL_COMPILE 0x100u /* test hook: the emitted source contains a failing static_assert */
 
 typedef struct sj_spec {

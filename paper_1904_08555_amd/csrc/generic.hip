@@ -28,8 +28,8 @@ struct Strides {
     int z_fast;             // 1: consecutive threads take consecutive z
 };
 
-__global__ void __launch_bounds__(kBlock)
-generic_ltimes(const double *__restrict__ L, const double *__restrict__ psi, double *__restrict__ phi, Strides s)
+__device__ __forceinline__ void ltimes_body(const double *__restrict__ L, const double *__restrict__ psi,
+                                            double *__restrict__ phi, const Strides &s)
 {
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= s.G * s.Z) return;
@@ -57,8 +57,8 @@ generic_ltimes(const double *__restrict__ L, const double *__restrict__ psi, dou
     }
 }
 
-__global__ void __launch_bounds__(kBlock)
-generic_lplustimes(const double *__restrict__ Lp, const double *__restrict__ phi, double *__restrict__ out, Strides s)
+__device__ __forceinline__ void lplustimes_body(const double *__restrict__ Lp, const double *__restrict__ phi,
+                                                double *__restrict__ out, const Strides &s)
 {
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= s.G * s.Z) return;
@@ -81,6 +81,66 @@ generic_lplustimes(const double *__restrict__ Lp, const double *__restrict__ phi
             else q[d * s.bd] += o;
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock)
+generic_ltimes(const double *__restrict__ L, const double *__restrict__ psi, double *__restrict__ phi, Strides s)
+{
+    ltimes_body(L, psi, phi, s);
+}
+
+__global__ void __launch_bounds__(kBlock)
+generic_lplustimes(const double *__restrict__ Lp, const double *__restrict__ phi, double *__restrict__ out, Strides s)
+{
+    lplustimes_body(Lp, phi, out, s);
+}
+
+// Offsets of logical (a, g, z) for an (A, G, Z) array stored in nesting LAYOUT,
+// the nesting known at compile time and the sizes at run time.
+template <int LAYOUT>
+__device__ __forceinline__ void layout_strides_ct(long long A, long long G, long long Z, long long &sa, long long &sg,
+                                                  long long &sz)
+{
+    if constexpr (LAYOUT == SJ_DGZ) { sa = G * Z; sg = Z; sz = 1; }
+    else if constexpr (LAYOUT == SJ_DZG) { sa = Z * G; sz = G; sg = 1; }
+    else if constexpr (LAYOUT == SJ_GDZ) { sg = A * Z; sa = Z; sz = 1; }
+    else if constexpr (LAYOUT == SJ_GZD) { sg = Z * A; sz = A; sa = 1; }
+    else if constexpr (LAYOUT == SJ_ZDG) { sz = A * G; sa = G; sg = 1; }
+    else { sz = G * A; sg = A; sa = 1; }
+}
+
+// Ahead-of-time kernels per nesting with run-time sizes: Kripke's own
+// multiversioning (ClangJIT section 5.2, layout-dispatch listing), the middle
+// baseline between the generic kernels (nesting and sizes at run time) and the
+// specializations (both at compile time).  The same loops as the generic
+// kernels; only the stride pattern and the thread order are constants.
+template <int LAYOUT, bool LT>
+__global__ void __launch_bounds__(kBlock)
+aot_layout_kernel(const double *__restrict__ W, const double *__restrict__ in, double *__restrict__ out, long long Z,
+                  long long G, long long D, long long NM)
+{
+    Strides s;
+    s.Z = Z; s.G = G; s.D = D; s.NM = NM;
+    layout_strides_ct<LAYOUT>(LT ? D : NM, G, Z, s.ad, s.ag, s.az);
+    layout_strides_ct<LAYOUT>(LT ? NM : D, G, Z, s.bd, s.bg, s.bz);
+    s.z_fast = (LAYOUT == SJ_DGZ || LAYOUT == SJ_GDZ || LAYOUT == SJ_GZD) ? 1 : 0;
+    if constexpr (LT) ltimes_body(W, in, out, s);
+    else lplustimes_body(W, in, out, s);
+}
+
+template <bool LT>
+hipError_t launch_aot(int layout, unsigned nblk, hipStream_t st, const double *W, const double *in, double *out,
+                      long long Z, long long G, long long D, long long NM)
+{
+    switch (layout) {
+    case SJ_DGZ: hipLaunchKernelGGL((aot_layout_kernel<SJ_DGZ, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    case SJ_DZG: hipLaunchKernelGGL((aot_layout_kernel<SJ_DZG, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    case SJ_GDZ: hipLaunchKernelGGL((aot_layout_kernel<SJ_GDZ, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    case SJ_GZD: hipLaunchKernelGGL((aot_layout_kernel<SJ_GZD, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    case SJ_ZDG: hipLaunchKernelGGL((aot_layout_kernel<SJ_ZDG, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    default: hipLaunchKernelGGL((aot_layout_kernel<SJ_ZGD, LT>), dim3(nblk), dim3(kBlock), 0, st, W, in, out, Z, G, D, NM); break;
+    }
+    return hipGetLastError();
 }
 
 // One workgroup (one wave) per instance, runtime n; A and B staged in LDS.
@@ -156,6 +216,12 @@ extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *cons
         const double *L = (const double *)ptrs[0];
         const double *in = (const double *)ptrs[1];
         double *outp = (double *)ptrs[2];
+        if (spec->flags & SJ_FLAG_GENERIC_PER_LAYOUT) {
+            hipError_t e = (k == SJ_LTIMES) ? launch_aot<true>(spec->layout, (unsigned)nblk, st, L, in, outp, Z, G, D, NM)
+                                            : launch_aot<false>(spec->layout, (unsigned)nblk, st, L, in, outp, Z, G, D, NM);
+            if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
+            return SJ_OK;
+        }
         if (k == SJ_LTIMES)
             hipLaunchKernelGGL(generic_ltimes, dim3((unsigned)nblk), dim3(kBlock), 0, st, L, in, outp, st_);
         else

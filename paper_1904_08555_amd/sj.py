@@ -57,6 +57,7 @@ SJ_FLAG_LOADS_NONTEMPORAL = 0x8
 SJ_FLAG_STORES_CACHED = 0x10
 SJ_FLAG_STORES_NONTEMPORAL = 0x20
 SJ_FLAG_ACCUMULATE = 0x40
+SJ_FLAG_GENERIC_PER_LAYOUT = 0x80
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 
 EXPORTED = (

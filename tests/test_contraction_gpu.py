@@ -26,9 +26,11 @@ def P():
 
 
 def run_ltimes(P, layout, Z, G, D, NM, L_d, psi_d, generic=False, **tile):
+    """generic: False (specialized), True (generic kernel), "layout" (generic kernel compiled per nesting)."""
     phi_d = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
     if generic:
-        P.sj_generic_run(P.SJ_LTIMES, [L_d, psi_d, phi_d], layout=layout, Z=Z, G=G, D=D, NM=NM)
+        fl = P.SJ_FLAG_GENERIC_PER_LAYOUT if generic == "layout" else 0
+        P.sj_generic_run(P.SJ_LTIMES, [L_d, psi_d, phi_d], layout=layout, Z=Z, G=G, D=D, NM=NM, flags=fl)
     else:
         h = P.sj_specialize(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, **tile)
         P.sj_run(h, [L_d, psi_d, phi_d])
@@ -38,7 +40,8 @@ def run_ltimes(P, layout, Z, G, D, NM, L_d, psi_d, generic=False, **tile):
 def run_lplus(P, layout, Z, G, D, NM, Lp_d, phi_d, generic=False, **tile):
     out_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
     if generic:
-        P.sj_generic_run(P.SJ_LPLUSTIMES, [Lp_d, phi_d, out_d], layout=layout, Z=Z, G=G, D=D, NM=NM)
+        fl = P.SJ_FLAG_GENERIC_PER_LAYOUT if generic == "layout" else 0
+        P.sj_generic_run(P.SJ_LPLUSTIMES, [Lp_d, phi_d, out_d], layout=layout, Z=Z, G=G, D=D, NM=NM, flags=fl)
     else:
         h = P.sj_specialize(P.SJ_LPLUSTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, **tile)
         P.sj_run(h, [Lp_d, phi_d, out_d])
@@ -56,7 +59,7 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("generic", [False, True], ids=["jit", "generic"])
+@pytest.mark.parametrize("generic", [False, True, "layout"], ids=["jit", "generic", "generic_per_layout"])
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("shape", SMALL, ids=lambda s: "Z%dG%dD%dNM%d" % s)
 def test_ltimes_lplustimes_small(P, orc, layout, shape, generic):
@@ -208,12 +211,12 @@ def test_six_layouts_full_size_sampled(P, orc, layout):
 
 def test_generic_full_size_sampled(P, orc):
     Z, G, D, NM = 32768, 32, 96, 16
-    for layout in ("DGZ", "GZD"):
+    for layout, mode in (("DGZ", True), ("GZD", True), ("DGZ", "layout"), ("ZGD", "layout")):
         li = LAYOUTS.index(layout)
         psi_d = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
         gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01, li, (D, G, Z))
         L = gen.matrix_sym(0, gen.ARR_L, NM, D)
-        phi_d = run_ltimes(P, layout, Z, G, D, NM, dev(L), psi_d, generic=True)
+        phi_d = run_ltimes(P, layout, Z, G, D, NM, dev(L), psi_d, generic=mode)
         rng = np.random.default_rng(9)
         g = rng.integers(0, G, 1024)
         z = rng.integers(0, Z, 1024)
