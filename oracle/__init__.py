@@ -50,6 +50,8 @@ def lib():
             f.argtypes = [i32, i64, i64, i64, i64, vp, vp, vp]
             f.restype = i32
         L.orc_bgemm.argtypes = [i64, vp, vp, vp, vp, vp]
+        for f in (L.orc_mass, L.orc_mass_absscale):
+            f.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp]
         for f in (L.orc_scattering, L.orc_scattering_absscale):
             f.argtypes = [i32, i64, i64, i64, i64, vp, vp, vp, vp]
         L.orc_bgemm.restype = i32
@@ -136,6 +138,24 @@ def scattering(layout, Z, G, NM, S, mat, phi, absolute=False) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_scattering failed (%d)" % rc)
     return out
+
+
+def mass(dim, D1D, Q1D, B1, Dq, X, absolute=False) -> np.ndarray:
+    """Tensor-product mass operator per element: Y[e] = B^T diag(Dq[e]) B X[e];
+    B1 [Q1D][D1D], Dq [NE][Q1D^dim], X [NE][D1D^dim] (first index fastest).
+    ``absolute`` returns the error scale |B|^T |Dq| |B| |X| instead."""
+    B1 = _f64(B1).reshape(-1)
+    nd, nq = D1D ** dim, Q1D ** dim
+    X = _f64(X).reshape(-1)
+    Dq = _f64(Dq).reshape(-1)
+    assert B1.size == Q1D * D1D and X.size % nd == 0 and Dq.size == (X.size // nd) * nq
+    NE = X.size // nd
+    Y = np.empty(NE * nd, dtype=np.float64)
+    f = lib().orc_mass_absscale if absolute else lib().orc_mass
+    rc = f(dim, D1D, Q1D, NE, _ptr(B1), _ptr(Dq), _ptr(X), _ptr(Y))
+    if rc != 0:
+        raise ValueError("orc_mass failed (%d)" % rc)
+    return Y
 
 
 def bgemm(n, off, A, B) -> np.ndarray:

@@ -30,6 +30,14 @@
  *    ordered by degree, nm = n^2 + n + m), mat(z) the zone's material, and S
  *    row-major [nmat][n_max + 1][G][G] (row g receives from column g').  phi
  *    and phi_out use the moment arrays' storage order.
+ *  - Tensor-product mass operator (a reading: the paper specializes Laghos'
+ *    partial-assembly kernels on the numbers of dofs and quadrature points,
+ *    section 5.3, without writing the operator down): per element e,
+ *        y_e[i] = sum_q B(q,i) D_e[q] sum_j B(q,j) x_e[j],
+ *        B(q,i) = prod_k B1[q_k][i_k]
+ *    over multi-indices i, j (D1D^dim dofs) and q (Q1D^dim points), with B1 the
+ *    row-major [Q1D][D1D] one-dimensional basis at the points and the first
+ *    index component fastest in x_e, y_e and D_e.
  *  - Batched small products: C_i = A_i * B_i, square, row-major, as in the
  *    paper's RAJA small matrix-multiply benchmark (section 5.1), one product per
  *    instance of a packed batch.
@@ -185,6 +193,62 @@ int orc_scattering_absscale(int layout, int64_t Z, int64_t G, int64_t NM, int64_
                             const int32_t *mat, const double *phi, double *scale)
 {
     return orc_scatter_impl(layout, Z, G, NM, nmat, S, mat, phi, scale, 1);
+}
+
+/* prod_k B1[q_k][i_k] for flat indices q (base Q1D) and i (base D1D), first component fastest;
+ * with `absolute` the product of magnitudes. */
+static double orc_basis(const double *B1, int64_t dim, int64_t D1D, int64_t Q1D, int64_t q, int64_t i, int absolute)
+{
+    double b = 1.0;
+    for (int64_t k = 0; k < dim; ++k) {
+        double v = B1[(q % Q1D) * D1D + (i % D1D)];
+        b = b * (absolute ? fabs(v) : v);
+        q /= Q1D;
+        i /= D1D;
+    }
+    return b;
+}
+
+/* y_e = B^T diag(D_e) B x_e for e < NE (the definition above, sums ascending); with
+ * `absolute` every factor by its magnitude (the componentwise error scale). */
+static int orc_mass_impl(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, const double *B1, const double *Dq,
+                         const double *X, double *Y, int absolute)
+{
+    if (dim < 1 || dim > 3 || D1D < 1 || Q1D < 1) return -1;
+    int64_t nd = 1, nq = 1;
+    for (int64_t k = 0; k < dim; ++k) { nd *= D1D; nq *= Q1D; }
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < NE; ++e) {
+        const double *x = X + e * nd;
+        const double *dq = Dq + e * nq;
+        double *y = Y + e * nd;
+        double u_stack[4096];
+        double *u = u_stack;
+        if (nq > 4096) continue;   /* the oracle serves small elements only */
+        for (int64_t q = 0; q < nq; ++q) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < nd; ++j) acc = acc + orc_basis(B1, dim, D1D, Q1D, q, j, absolute) * (absolute ? fabs(x[j]) : x[j]);
+            u[q] = acc * (absolute ? fabs(dq[q]) : dq[q]);
+        }
+        for (int64_t i = 0; i < nd; ++i) {
+            double acc = 0.0;
+            for (int64_t q = 0; q < nq; ++q) acc = acc + orc_basis(B1, dim, D1D, Q1D, q, i, absolute) * u[q];
+            y[i] = acc;
+        }
+    }
+    return nq > 4096 ? -2 : 0;
+}
+
+int orc_mass(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, const double *B1, const double *Dq, const double *X,
+             double *Y)
+{
+    return orc_mass_impl(dim, D1D, Q1D, NE, B1, Dq, X, Y, 0);
+}
+
+int orc_mass_absscale(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, const double *B1, const double *Dq,
+                      const double *X, double *Y)
+{
+    return orc_mass_impl(dim, D1D, Q1D, NE, B1, Dq, X, Y, 1);
 }
 
 /* C_i = A_i * B_i for i < count; instance i is n[i] x n[i], row-major, stored at
