@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "<out-dir>/tuned_moments.json) instead of tuning")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering"),
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering", "mass"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -132,6 +132,8 @@ def main():
         return bench_values(a)
     if a.workload == "scattering":
         return bench_scattering(a)
+    if a.workload == "mass":
+        return bench_mass(a)
     return bench_moments(a)
 
 
@@ -767,6 +769,55 @@ def bench_scattering(a):
                      "frac": res[dom]["frac"], "traffic": None, "kernel": res[dom]["kernel"],
                      "avg_us": res[dom]["us"], "bytes_per_launch": nbytes},
         "per_layout": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_mass(a):
+    """Tensor-product mass operator (partial assembly): hexahedra with D1D = 4
+    dofs and Q1D = 6 points per direction (500,000 elements) and quadrilaterals
+    with D1D = 4, Q1D = 6 (2,000,000 elements), FP64.  The specialization fixes
+    dim, D1D, Q1D and the element count.  value = algorithmic bytes (x and the
+    point data read, y written, B1 once) of both launches / their median times."""
+    import numpy as np
+    import torch
+
+    import paper_1904_08555_amd as P
+
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(0)
+    res, tot_b, tot_t = {}, 0, 0.0
+    for dim, D1D, Q1D, NE in ((3, 4, 6, 500000), (2, 4, 6, 2000000)):
+        nd, nq = D1D ** dim, Q1D ** dim
+        B1 = torch.from_numpy(rng.uniform(-1, 1, Q1D * D1D)).cuda()
+        g = torch.Generator("cuda").manual_seed(0)
+        Dq = torch.rand(NE * nq, dtype=torch.float64, device="cuda", generator=g)
+        X = torch.rand(NE * nd, dtype=torch.float64, device="cuda", generator=g)
+        Y = torch.empty_like(X)
+        h = P.sj_specialize(P.SJ_MASS, D=D1D, NM=Q1D, inputs=dim, count=NE)
+        t, _ = time_launches(lambda: P.sj_run(h, [B1, Dq, X, Y]), a.steps, stream)
+        nb = NE * (2 * nd + nq) * 8 + Q1D * D1D * 8
+        flops = 2 * NE * 2 * sum(D1D ** (dim - s) * Q1D ** (s + 1) for s in range(dim)) if dim > 0 else 0
+        info = P.sj_handle_info(h)
+        res[f"{dim}d_d{D1D}_q{Q1D}_ne{NE}"] = dict(us=round(t * 1e3, 1), gbs=round(nb / (t * 1e-3) / 1e9, 1),
+                                                   frac=round(nb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                                   gflops=round(flops / (t * 1e-3) / 1e9, 1), bytes=nb,
+                                                   kernel=info["kernel_name"], elements_per_wave=info["tile_n"],
+                                                   block=info["block"], vgprs=info["vgprs"], lds=info["lds_bytes"])
+        tot_b += nb
+        tot_t += t
+        del Dq, X, Y
+    dom = max(res, key=lambda k: res[k]["us"])
+    line = {
+        "metric": "tensor-product mass operator (partial assembly) GB/s",
+        "value": round(tot_b / (tot_t * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": 0, "ms_per_step": round(tot_t, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (torch Philox U[0,1) x and point data, seeded B1)",
+        "config": {"workload": "mass operator y_e = B^T D_e B x_e: hex D1D=4 Q1D=6 NE=500000; quad D1D=4 Q1D=6 NE=2000000"},
+        "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": res[dom]["frac"], "traffic": None, "kernel": res[dom]["kernel"], "avg_us": res[dom]["us"],
+                     "bytes_per_launch": res[dom]["bytes"]},
+        "cases": res,
     }
     print(json.dumps(line), flush=True)
 

@@ -79,7 +79,8 @@ typedef enum sj_kernel {
     SJ_MLP_BWD = 5,
     SJ_ADAM = 6,
     SJ_LTIMES_LPLUS = 7,   /* LTimes then LPlusTimes on the same columns in one pass (phi stays on chip) */
-    SJ_SCATTERING = 8      /* scattering source phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] phi[nm,g',z] */
+    SJ_SCATTERING = 8,     /* scattering source phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] phi[nm,g',z] */
+    SJ_MASS = 9            /* tensor-product mass operator per element, y_e = B^T diag(D_e) B x_e (partial assembly) */
 } sj_kernel;
 
 /* Storage order of a psi-like array's three axes, rightmost fastest.  phi uses
@@ -244,6 +245,12 @@ sj_status sj_specialize_with_code(sj_kernel k, const sj_spec *spec, const void *
  *                  from group g'); phi and phi_out in the spec's nesting with D read as NM; the degree of
  *                  moment nm is floor(sqrt(nm)).  A zone whose material is outside [0, count) gets NaN
  *                  outputs (nothing is read out of range).  Overwrites phi_out.
+ *   SJ_MASS:       {B1 [Q1D*D1D] f64, D [NE*Q1D^dim] f64, X [NE*D1D^dim] f64, Y [NE*D1D^dim] f64} with
+ *                  spec->D = D1D (dofs per direction, 1..32), spec->NM = Q1D (points per direction, 1..32),
+ *                  spec->inputs = dim (1, 2, 3), spec->count = NE (elements); B1 row-major [Q1D][D1D] (the
+ *                  1-D basis at the points); per element the first index component is fastest; tile_n =
+ *                  elements per wave (0 = default).  y_e = B^T diag(D_e) B x_e, B the dim-fold tensor
+ *                  product of B1 (the Laghos-style partial-assembly mass action); overwrites Y.
  *   SJ_MLP_FWD:    {theta f32, X [rows*inputs] f32, y [rows] f32}
  *   SJ_MLP_BWD:    {theta f32, X [rows*inputs] f32, t [rows] f32, grad f32 (same packing as theta), loss [1] f32,
  *                  workspace [rows*(4*width+2)] f32}

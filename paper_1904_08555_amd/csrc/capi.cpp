@@ -530,6 +530,21 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
         if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
         return SJ_OK;
     }
+    if (k.kernel == SJ_MASS) {
+        // {B1, D, X, Y}
+        size_t nd = 1, nq = 1;
+        for (int64_t i = 0; i < k.inputs; ++i) { nd *= (size_t)k.D; nq *= (size_t)k.NM; }
+        const size_t ne = (size_t)k.rows;
+        const size_t bytes[4] = {(size_t)k.D * (size_t)k.NM * 8, ne * nq * 8, ne * nd * 8, ne * nd * 8};
+        sj_status s = check_ptrs(ptrs, nptrs, 4, bytes, 3);
+        if (s != SJ_OK) return s;
+        void *a0 = ptrs[0], *a1 = ptrs[1], *a2 = ptrs[2], *a3 = ptrs[3];
+        void *args[] = {&a0, &a1, &a2, &a3};
+        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0,
+                                             (hipStream_t)stream, args, nullptr);
+        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+        return SJ_OK;
+    }
     if (k.kernel == SJ_SCATTERING) {
         // {S, mat, phi, phi_out}
         size_t nl = 0;

@@ -424,6 +424,34 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         (void)outn;
         return (*out = key), SJ_OK;
     }
+    if (k == SJ_MASS) {
+        // tensor-product mass operator (partial assembly): D = D1D, NM = Q1D, inputs = dim, count = NE
+        if (s->dtype != SJ_F64) return fail(SJ_ERR_INVALID_ARG, "the mass operator is FP64 (dtype SJ_F64)");
+        if (s->inputs < 1 || s->inputs > 3) return fail(SJ_ERR_INVALID_ARG, "inputs (dimension) must be 1, 2 or 3");
+        if (s->D < 1 || s->D > 32 || s->NM < 1 || s->NM > 32)
+            return fail(SJ_ERR_INVALID_ARG, "D (dofs per direction) and NM (points per direction) must be in [1, 32]");
+        if (s->count < 1 || s->count > (int64_t(1) << 31) - 1) return fail(SJ_ERR_INVALID_ARG, "count (elements) must be in [1, 2^31-1]");
+        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
+            return fail(SJ_ERR_UNSUPPORTED, "the mass operator has the DIRECT structure only");
+        if (s->tile_k != 0 || s->unroll != 0 || (s->order != 0 && s->order != 1) || (s->flags & SJ_FLAG_ACCUMULATE))
+            return fail(SJ_ERR_INVALID_ARG, "the mass operator takes tile_n and block only");
+        const int64_t dim = s->inputs, D1D = s->D, Q1D = s->NM, mx = std::max(D1D, Q1D);
+        int64_t nd = 1, nq = 1, ns = 1, mxlo = 1;
+        for (int64_t i = 0; i < dim; ++i) { nd *= D1D; nq *= Q1D; ns *= mx; }
+        for (int64_t i = 0; i + 1 < dim; ++i) mxlo *= mx;
+        int ew = s->tile_n ? s->tile_n : (int)std::max<int64_t>(1, std::min<int64_t>(32, 64 / mxlo));
+        if (ew < 1 || ew > 64) return fail(SJ_ERR_INVALID_ARG, "tile_n (elements per wave) must be in [1, 64]");
+        auto lds = [&](int block) { return (int64_t)(block / 64) * ew * (2 * ns + nq) * 8; };
+        int block = s->block;
+        if (block == 0) block = (lds(128) <= 64 * 1024) ? 128 : 64;
+        if (!valid_block(block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+        if (lds(block) > 160 * 1024) return fail(SJ_ERR_UNSUPPORTED, "mass operator tiles exceed 160 KiB of LDS");
+        if (s->count * std::max(nd, nq) > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "arrays too large");
+        key.D = D1D; key.NM = Q1D; key.inputs = dim; key.rows = s->count;
+        key.tile_n = ew; key.block = block; key.variant = SJ_VAR_DIRECT; key.order = 1;
+        key.index64 = (s->count * std::max(nd, nq) >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+        return (*out = key), SJ_OK;
+    }
     if (k == SJ_SCATTERING) {
         // scattering source over the six nestings of the moment arrays: one thread per (nm, z) line
         if (s->dtype != SJ_F64) return fail(SJ_ERR_INVALID_ARG, "scattering is FP64 (dtype SJ_F64)");
@@ -519,6 +547,10 @@ Geometry key_geometry(const SpecKey &k)
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
     if (k.kernel == SJ_SCATTERING) g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
+    if (k.kernel == SJ_MASS) {
+        const int64_t per_block = (int64_t)(k.block / 64) * k.tile_n;
+        g.grid = (unsigned)((k.rows + per_block - 1) / per_block);
+    }
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         if (k.variant == SJ_VAR_DIRECT) {
             const int64_t nv = k.B * (k.I / k.tile_n);
@@ -660,6 +692,15 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n";
             body = (k.tile_n == 4) ? kTpl_ltimes_bf16w : kTpl_ltimes_bf16;
         }
+    }
+    if (k.kernel == SJ_MASS) {
+        o << "#define SJ_DIM " << k.inputs << "\n#define SJ_D1D " << k.D << "\n#define SJ_Q1D " << k.NM << "\n#define SJ_NE "
+          << k.rows << sfx << "\n#define SJ_EW " << k.tile_n << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD "
+          << ((k.flags & SJ_FLAG_LOADS_CACHED) ? 0 : 1) << "\n#define SJ_NT_STORE " << ((k.flags & SJ_FLAG_STORES_CACHED) ? 0 : 1)
+          << "\n#define SJ_ACCUM 0\n";
+        body = kTpl_mass_pa;
+        *name = "sj_mass_pa_" + std::to_string(k.inputs) + "d_d" + std::to_string(k.D) + "_q" + std::to_string(k.NM);
+        o << "#define SJ_KERNEL_NAME " << *name << "\n";
     }
     if (k.kernel == SJ_SCATTERING) {
         // strides of the (nm, g, z) axes in the nesting, rightmost fastest

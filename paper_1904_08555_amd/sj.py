@@ -36,6 +36,7 @@ SJ_MLP_BWD = 5
 SJ_ADAM = 6
 SJ_LTIMES_LPLUS = 7
 SJ_SCATTERING = 8
+SJ_MASS = 9
 # sj_layout
 LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 SJ_DGZ, SJ_DZG, SJ_GDZ, SJ_GZD, SJ_ZDG, SJ_ZGD = range(6)

@@ -380,3 +380,19 @@ def test_scattering_specs(P):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_SCATTERING, **dict(base, **bad))
         assert e.value.status == status, bad
+
+
+def test_mass_specs(P):
+    co = P.SJ_FLAG_COMPILE_ONLY
+    base = dict(D=4, NM=6, inputs=3, count=1000, flags=co)
+    h = P.sj_specialize(P.SJ_MASS, **base)
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_mass_pa_3d_d4_q6"
+    src = P.sj_emit_source(P.SJ_MASS, **base)
+    assert "#define SJ_DIM 3" in src and "#define SJ_D1D 4" in src and "#define SJ_Q1D 6" in src
+    for bad, status in ((dict(inputs=4), P.SJ_ERR_INVALID_ARG), (dict(D=33), P.SJ_ERR_INVALID_ARG),
+                        (dict(count=0), P.SJ_ERR_INVALID_ARG), (dict(variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED),
+                        (dict(unroll=2), P.SJ_ERR_INVALID_ARG), (dict(D=32, NM=32, block=1024), P.SJ_ERR_UNSUPPORTED),
+                        (dict(dtype=P.SJ_F32), P.SJ_ERR_INVALID_ARG)):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_MASS, **dict(base, **bad))
+        assert e.value.status == status, bad
