@@ -56,6 +56,26 @@ MEASURED_TRAFFIC = {
     "385b9213b1c196f5763daab7b57762938b92611d": 939708156,  # sj_ltimes_rows_mfma_lds_zgd
     "c524a2bbfc0f9a1e5e68eb37e59b080356775bee": 939764733,  # sj_lplustimes_rows_mfma_zgd
     "456ff6bccbb93f1b5b963602531428289040ee2d": 940383099,  # sj_lplustimes_cols_mfma_zdg (unroll 2)
+    # fused LTimes + LPlusTimes (phi written too), scattering (4 materials in zone regions),
+    # mass operator, BF16 LTimes: the default specializations of their workloads
+    "08de64ddce1c10477dfd9fb1f82c56008bd3d5f1": 1746069941,  # sj_ltimes_lplus_direct_dgz
+    "bfbba7d7caf51feaf1630a0d1c790da03062259b": 1746087286,  # sj_ltimes_lplus_direct_dzg
+    "17a60d0960937ba3962cf753e6e07200227dc6fe": 1746373814,  # sj_ltimes_lplus_direct_gdz
+    "cff7a5f6311098a7c3d8e1207d23517039285f75": 1746157747,  # sj_ltimes_lplus_rows_mfma_lds_gzd
+    "7974d54267365633a13564ed43b1ffa87ee583bc": 1746272694,  # sj_ltimes_lplus_direct_zdg
+    "e4d18d900fda6f5b2812b77a6162f628b58592c4": 1746151474,  # sj_ltimes_lplus_rows_mfma_lds_zgd
+    "c8223a9a41e23728d3c3ba6f288438478c642677": 271004427,  # sj_scattering_direct_dgz
+    "6fef6c0acc607b44b2f436dfb0a6668de81792d1": 270871627,  # sj_scattering_direct_dzg
+    "7ca4b84f860aebf4a9baddc2bf537779ede67ad1": 271274251,  # sj_scattering_direct_gdz
+    "7ed4edd6342cd118f796ec433bac2e9182f7aaf4": 271297373,  # sj_scattering_direct_gzd
+    "67c8cb5af24d221a84b5a46de82ae225cccfbbd0": 270238173,  # sj_scattering_direct_zdg
+    "f77a6ba0df0c8ab3f896bb994f24ca955af08497": 270219806,  # sj_scattering_direct_zgd
+    "db2131e0fc892566b4bc53ee6dafc54c66662b03": 1424929368,  # sj_mass_pa_3d_d4_q6
+    "93d86dd58ff927362edaf65b66937e50fd07b9e7": 1088023734,  # sj_mass_pa_2d_d4_q6
+    "793f46646f1f1acf9ffee52144a18fa02ea8f8f0": 12885965361,  # sj_ltimes_bf16w_dgz
+    "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
+    "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
+    "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
@@ -605,13 +625,15 @@ def bench_bf16(a):
     # default (wide, four columns per lane) and the one-column-per-lane form
     for name, dt, cols in (("bf16", P.SJ_BF16, 0), ("bf16x3", P.SJ_BF16X3, 0),
                            ("bf16_narrow", P.SJ_BF16, 1), ("bf16x3_narrow", P.SJ_BF16X3, 1)):
-        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt, tile_n=cols)
+        spec = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM, dtype=dt, tile_n=cols)
+        h = P.sj_specialize(P.SJ_LTIMES, spec)
         t = P.sj_time_run(h, [L_d, psi32, phi32], warmup=a.warmup, reps=a.steps)
         ms = statistics.median(t)
         info = P.sj_handle_info(h)
         res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
                          frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
-                         vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"])
+                         vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"],
+                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec))
     del phi32
     psi64 = psi32.to(torch.float64)
     del psi32
@@ -635,7 +657,7 @@ def bench_bf16(a):
         "dtype": "bf16x3 (fp32 accumulate)", "data": "synthetic (SplitMix64, seed 0)",
         "config": {"workload": "LTimes DGZ Z=262144 G=64 D=128 NM=64, psi FP32 in, phi FP32 out"},
         "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": best["frac"], "traffic": None, "kernel": best["kernel"], "bytes_per_launch": b32},
+                     "frac": best["frac"], "traffic": best["traffic"], "kernel": best["kernel"], "bytes_per_launch": b32},
         "modes": res,
     }
     print(json.dumps(line), flush=True)
@@ -748,7 +770,8 @@ def bench_scattering(a):
     res, tot = {}, 0.0
     for lay in layouts:
         gdev.fill(phi, 0, gen.ARR_PHI, gdev.DIST_U01, LAYOUTS.index(lay), (NM, G, Z))
-        h = P.sj_specialize(P.SJ_SCATTERING, layout=lay, Z=Z, G=G, NM=NM, count=nmat)
+        spec = P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat)
+        h = P.sj_specialize(P.SJ_SCATTERING, spec)
         t, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_reg, phi, out]), a.steps, stream)
         tr, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream)
         info = P.sj_handle_info(h)
@@ -756,7 +779,8 @@ def bench_scattering(a):
         res[lay] = dict(us=round(t * 1e3, 1), gbs=round(nbytes / (t * 1e-3) / 1e9, 1),
                         frac=round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                         random_materials_us=round(tr * 1e3, 1), kernel=info["kernel_name"], vgprs=info["vgprs"],
-                        compile_ms=round(info["compile_ms"], 1))
+                        compile_ms=round(info["compile_ms"], 1), src_sha1=source_sha1(P, P.SJ_SCATTERING, spec),
+                        traffic=measured_traffic(P, P.SJ_SCATTERING, spec))
     dom = max(res, key=lambda k: res[k]["us"])
     line = {
         "metric": "scattering source GB/s over six nestings (specialized kernels)",
@@ -766,7 +790,7 @@ def bench_scattering(a):
         "config": {"workload": f"scattering, FP64, Z={Z} G={G} NM={NM}, {nmat} materials in zone regions",
                    "layouts": layouts},
         "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": res[dom]["frac"], "traffic": None, "kernel": res[dom]["kernel"],
+                     "frac": res[dom]["frac"], "traffic": res[dom]["traffic"], "kernel": res[dom]["kernel"],
                      "avg_us": res[dom]["us"], "bytes_per_launch": nbytes},
         "per_layout": res,
     }
@@ -794,7 +818,8 @@ def bench_mass(a):
         Dq = torch.rand(NE * nq, dtype=torch.float64, device="cuda", generator=g)
         X = torch.rand(NE * nd, dtype=torch.float64, device="cuda", generator=g)
         Y = torch.empty_like(X)
-        h = P.sj_specialize(P.SJ_MASS, D=D1D, NM=Q1D, inputs=dim, count=NE)
+        spec = P.make_spec(D=D1D, NM=Q1D, inputs=dim, count=NE)
+        h = P.sj_specialize(P.SJ_MASS, spec)
         t, _ = time_launches(lambda: P.sj_run(h, [B1, Dq, X, Y]), a.steps, stream)
         nb = NE * (2 * nd + nq) * 8 + Q1D * D1D * 8
         flops = 2 * NE * 2 * sum(D1D ** (dim - s) * Q1D ** (s + 1) for s in range(dim)) if dim > 0 else 0
@@ -803,7 +828,9 @@ def bench_mass(a):
                                                    frac=round(nb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                                    gflops=round(flops / (t * 1e-3) / 1e9, 1), bytes=nb,
                                                    kernel=info["kernel_name"], elements_per_wave=info["tile_n"],
-                                                   block=info["block"], vgprs=info["vgprs"], lds=info["lds_bytes"])
+                                                   block=info["block"], vgprs=info["vgprs"], lds=info["lds_bytes"],
+                                                   src_sha1=source_sha1(P, P.SJ_MASS, spec),
+                                                   traffic=measured_traffic(P, P.SJ_MASS, spec))
         tot_b += nb
         tot_t += t
         del Dq, X, Y
@@ -815,7 +842,7 @@ def bench_mass(a):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (torch Philox U[0,1) x and point data, seeded B1)",
         "config": {"workload": "mass operator y_e = B^T D_e B x_e: hex D1D=4 Q1D=6 NE=500000; quad D1D=4 Q1D=6 NE=2000000"},
         "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": res[dom]["frac"], "traffic": None, "kernel": res[dom]["kernel"], "avg_us": res[dom]["us"],
+                     "frac": res[dom]["frac"], "traffic": res[dom]["traffic"], "kernel": res[dom]["kernel"], "avg_us": res[dom]["us"],
                      "bytes_per_launch": res[dom]["bytes"]},
         "cases": res,
     }
@@ -851,7 +878,8 @@ def bench_fused(a):
     tot_fused, tot_sep = 0.0, 0.0
     for lay in layouts:
         gdev.fill(psi, 0, gen.ARR_PSI, gdev.DIST_U01, LAYOUTS.index(lay), (D, G, Z))
-        hf = P.sj_specialize(P.SJ_LTIMES_LPLUS, layout=lay, Z=Z, G=G, D=D, NM=NM)
+        fspec = P.make_spec(layout=lay, Z=Z, G=G, D=D, NM=NM)
+        hf = P.sj_specialize(P.SJ_LTIMES_LPLUS, fspec)
         h1 = P.sj_specialize(P.SJ_LTIMES, layout=lay, Z=Z, G=G, D=D, NM=NM)
         h2 = P.sj_specialize(P.SJ_LPLUSTIMES, layout=lay, Z=Z, G=G, D=D, NM=NM)
 
@@ -867,7 +895,9 @@ def bench_fused(a):
                         fused_no_phi_us=round(fused_without * 1e3, 1),
                         fused_no_phi_gbs=round(b_without / (fused_without * 1e-3) / 1e9, 1),
                         separate_us=round(sep_ms * 1e3, 1), speedup=round(sep_ms / fused_with, 3),
-                        kernel=P.sj_handle_info(hf)["kernel_name"])
+                        kernel=P.sj_handle_info(hf)["kernel_name"],
+                        src_sha1=source_sha1(P, P.SJ_LTIMES_LPLUS, fspec),
+                        traffic=measured_traffic(P, P.SJ_LTIMES_LPLUS, fspec))
     dom = max(res, key=lambda k: res[k]["fused_us"])
     line = {
         "metric": "fused LTimes+LPlusTimes GB/s (phi kept on chip) vs the two separate kernels",
@@ -876,7 +906,7 @@ def bench_fused(a):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64, seed 0)",
         "config": {"workload": f"psi -> phi -> psi' per nesting, FP64, Z={Z} G={G} D={D} NM={NM}", "layouts": layouts},
         "roofline": {"bound": "hbm", "achieved": res[dom]["fused_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(res[dom]["fused_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(res[dom]["fused_gbs"] / HBM_PEAK_GBS, 4), "traffic": res[dom]["traffic"],
                      "kernel": res[dom]["kernel"], "avg_us": res[dom]["fused_us"], "bytes_per_launch": b_with},
         "separate_ms_per_step": round(tot_sep, 4), "speedup_vs_separate": round(tot_sep / tot_fused, 3),
         "bytes": {"fused_with_phi": b_with, "fused_without_phi": b_without, "separate_pair": b_sep},
