@@ -411,6 +411,9 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             if (cpl == 0) cpl = (key.I % 4 == 0) ? 4 : 1;
             if (cpl != 1 && cpl != 4) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n (columns per lane) must be 1 or 4");
             if (cpl == 4 && key.I % 4 != 0) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n 4 needs a column extent divisible by 4");
+            // four columns per lane hold 128 FP32 accumulators: a 1024-thread block leaves 128 registers
+            // per lane and the kernel spills (measured 21.9 ms against 2.38 ms at block 256)
+            if (cpl == 4 && key.block > 512) return fail(SJ_ERR_UNSUPPORTED, "BF16 tile_n 4 needs a block of at most 512 threads");
             key.tile_n = cpl;
             const int64_t frag_bytes = ((s->NM + 31) / 32) * ((s->D + 15) / 16) * 64 * 16;
             if (frag_bytes * (s->dtype == SJ_BF16X3 ? 2 : 1) > 160 * 1024)

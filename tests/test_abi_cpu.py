@@ -396,3 +396,13 @@ def test_mass_specs(P):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_MASS, **dict(base, **bad))
         assert e.value.status == status, bad
+
+
+def test_bf16_wide_block_limit(P):
+    """Four columns per lane need at most 512 threads per block (1024 would spill)."""
+    co = P.SJ_FLAG_COMPILE_ONLY
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=4096, G=8, D=48, NM=16, dtype=P.SJ_BF16X3, tile_n=4, block=1024,
+                        flags=co)
+    assert e.value.status == P.SJ_ERR_UNSUPPORTED
+    P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=4096, G=8, D=48, NM=16, dtype=P.SJ_BF16X3, tile_n=4, block=512, flags=co)
