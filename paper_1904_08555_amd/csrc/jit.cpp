@@ -408,7 +408,7 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             // tile_n = columns per lane: 1 (4-byte loads, 32 columns per wave) or 4 (16-byte loads,
             // 128 columns per wave as four interleaved MFMA tiles; needs the column extent % 4 == 0).
             int cpl = s->tile_n;
-            if (cpl == 0) cpl = (key.I % 4 == 0) ? 4 : 1;
+            if (cpl == 0) cpl = (key.I % 4 == 0 && key.block <= 512) ? 4 : 1;
             if (cpl != 1 && cpl != 4) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n (columns per lane) must be 1 or 4");
             if (cpl == 4 && key.I % 4 != 0) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n 4 needs a column extent divisible by 4");
             // four columns per lane hold 128 FP32 accumulators: a 1024-thread block leaves 128 registers
