@@ -64,18 +64,18 @@ MEASURED_TRAFFIC = {
     "cff7a5f6311098a7c3d8e1207d23517039285f75": 1746157747,  # sj_ltimes_lplus_rows_mfma_lds_gzd
     "7974d54267365633a13564ed43b1ffa87ee583bc": 1746272694,  # sj_ltimes_lplus_direct_zdg
     "e4d18d900fda6f5b2812b77a6162f628b58592c4": 1746151474,  # sj_ltimes_lplus_rows_mfma_lds_zgd
-    "c8223a9a41e23728d3c3ba6f288438478c642677": 271004427,  # sj_scattering_direct_dgz
-    "6fef6c0acc607b44b2f436dfb0a6668de81792d1": 270871627,  # sj_scattering_direct_dzg
-    "7ca4b84f860aebf4a9baddc2bf537779ede67ad1": 271274251,  # sj_scattering_direct_gdz
-    "7ed4edd6342cd118f796ec433bac2e9182f7aaf4": 271297373,  # sj_scattering_direct_gzd
-    "67c8cb5af24d221a84b5a46de82ae225cccfbbd0": 270238173,  # sj_scattering_direct_zdg
-    "f77a6ba0df0c8ab3f896bb994f24ca955af08497": 270219806,  # sj_scattering_direct_zgd
     "db2131e0fc892566b4bc53ee6dafc54c66662b03": 1424929368,  # sj_mass_pa_3d_d4_q6
     "93d86dd58ff927362edaf65b66937e50fd07b9e7": 1088023734,  # sj_mass_pa_2d_d4_q6
     "793f46646f1f1acf9ffee52144a18fa02ea8f8f0": 12885965361,  # sj_ltimes_bf16w_dgz
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
+    "1aba452de4b48e505b1c3a3a58e6fddd73856736": 270830123,  # sj_scattering_direct_dgz
+    "9308f8e2c8bc12d17665d3e830e0252c3c43b24f": 270858346,  # sj_scattering_direct_dzg
+    "da309c111cd44a648cce7fe319f8564822245b69": 270840107,  # sj_scattering_direct_gdz
+    "9ee394180dbc2b72f6e97223a495365d2edd6151": 270001917,  # sj_scattering_direct_gzd
+    "cf36ea5c5d3bd1976b2063d8668e97103077279e": 270289149,  # sj_scattering_direct_zdg
+    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 269986558,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
