@@ -729,7 +729,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
           << k.rows << "\n#define SJ_NL " << nl << "\n#define SJ_SNM " << snm << sfx << "\n#define SJ_SG " << sg << sfx
           << "\n#define SJ_SZ " << sz << sfx << "\n#define SJ_LANE_NM " << (snm < sz ? 1 : 0) << "\n#define SJ_RUN_LINES "
           << ((sg == 1 && std::min(snm, sz) == G) ? 1 : 0) << "\n#define SJ_SLDS "
-          << (nl * (G * G + 2) * 8 <= 64 * 1024 ? 1 : 0) << "\n#define SJ_BLOCK "
+          << ((snm < sz && nl * (G * G + 2) * 8 <= 64 * 1024) ? 1 : 0) << "\n#define SJ_BLOCK "
           << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n";
         body = kTpl_scattering_direct;
         static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
