@@ -70,12 +70,12 @@ MEASURED_TRAFFIC = {
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "1aba452de4b48e505b1c3a3a58e6fddd73856736": 270830123,  # sj_scattering_direct_dgz
-    "9308f8e2c8bc12d17665d3e830e0252c3c43b24f": 270858346,  # sj_scattering_direct_dzg
-    "da309c111cd44a648cce7fe319f8564822245b69": 270840107,  # sj_scattering_direct_gdz
-    "9ee394180dbc2b72f6e97223a495365d2edd6151": 270001917,  # sj_scattering_direct_gzd
-    "cf36ea5c5d3bd1976b2063d8668e97103077279e": 270289149,  # sj_scattering_direct_zdg
-    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 269986558,  # sj_scattering_direct_zgd
+    "7cf0defc5808a86711ab4fb004ef6de6e18a9152": 270835435,  # sj_scattering_direct_dgz
+    "503826a1ec572b26fc89963507493b01cb4fa9c7": 271160043,  # sj_scattering_direct_dzg
+    "89859078ba492326937d0ede52a949485b44fa27": 270949930,  # sj_scattering_direct_gdz
+    "9ee394180dbc2b72f6e97223a495365d2edd6151": 270059197,  # sj_scattering_direct_gzd
+    "cf36ea5c5d3bd1976b2063d8668e97103077279e": 270253309,  # sj_scattering_direct_zdg
+    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 270069950,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
