@@ -482,8 +482,31 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         key.Z = s->Z; key.G = s->G; key.NM = s->NM;
         key.rows = s->count;   // materials
         key.variant = SJ_VAR_DIRECT;
-        key.block = s->block ? s->block : 256;
+        // LDS of the emitted kernel (see the emission): per-wave line tiles where g is innermost and
+        // consecutive lines are contiguous, and the staged degree matrices where lanes run along nm
+        int64_t snm = 0, sg = 0, sz = 0;
+        const int64_t NMv = s->NM, Gv = s->G, Zv = s->Z;
+        switch (s->layout) {
+        case SJ_DGZ: snm = Gv * Zv; sg = Zv; sz = 1; break;
+        case SJ_DZG: snm = Zv * Gv; sz = Gv; sg = 1; break;
+        case SJ_GDZ: sg = NMv * Zv; snm = Zv; sz = 1; break;
+        case SJ_GZD: sg = Zv * NMv; sz = NMv; snm = 1; break;
+        case SJ_ZDG: sz = NMv * Gv; snm = Gv; sg = 1; break;
+        default: sz = Gv * NMv; sg = NMv; snm = 1; break;
+        }
+        const bool run_lines = (sg == 1 && std::min(snm, sz) == Gv);
+        const bool slds = (snm < sz && nl * (Gv * Gv + 2) * 8 <= 64 * 1024);
+        const int64_t tp = Gv + (Gv % 2 == 0 ? 2 : 1);
+        auto lds = [&](int block) {
+            return (run_lines ? (int64_t)(block / 64) * 64 * tp * 8 : 0) + (slds ? nl * (Gv * Gv + 2) * 8 + 8 : 0);
+        };
+        // measured on MI355X at Z=32768 G=32 NM=16: ZDG (line tiles and staged matrices) 102.7 us at
+        // 384 threads against 116.9 us at 256; 256 for the other nestings
+        // (512 bytes kept back for the compiler's alignment of the shared arrays)
+        key.block = s->block ? s->block : ((run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : 256);
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+        if (lds(key.block) + 512 > 160 * 1024)
+            return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
         key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
         key.order = 1;
         return (*out = key), SJ_OK;

@@ -376,7 +376,8 @@ def test_scattering_specs(P):
     for bad, status in ((dict(count=0), P.SJ_ERR_INVALID_ARG), (dict(G=65), P.SJ_ERR_UNSUPPORTED),
                         (dict(variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED), (dict(tile_n=2), P.SJ_ERR_INVALID_ARG),
                         (dict(flags=co | P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG), (dict(dtype=P.SJ_BF16), P.SJ_ERR_INVALID_ARG),
-                        (dict(layout=7), P.SJ_ERR_INVALID_ARG)):
+                        (dict(layout=7), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZDG", Z=32768, G=32, NM=16, count=4, block=512), P.SJ_ERR_UNSUPPORTED)):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_SCATTERING, **dict(base, **bad))
         assert e.value.status == status, bad
