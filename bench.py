@@ -70,12 +70,12 @@ MEASURED_TRAFFIC = {
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "7cf0defc5808a86711ab4fb004ef6de6e18a9152": 270835435,  # sj_scattering_direct_dgz
-    "503826a1ec572b26fc89963507493b01cb4fa9c7": 271160043,  # sj_scattering_direct_dzg
-    "89859078ba492326937d0ede52a949485b44fa27": 270949930,  # sj_scattering_direct_gdz
-    "9ee394180dbc2b72f6e97223a495365d2edd6151": 270059197,  # sj_scattering_direct_gzd
-    "cf36ea5c5d3bd1976b2063d8668e97103077279e": 270253309,  # sj_scattering_direct_zdg
-    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 270069950,  # sj_scattering_direct_zgd
+    "7cf0defc5808a86711ab4fb004ef6de6e18a9152": 270840139,  # sj_scattering_direct_dgz
+    "503826a1ec572b26fc89963507493b01cb4fa9c7": 271240395,  # sj_scattering_direct_dzg
+    "89859078ba492326937d0ede52a949485b44fa27": 270903883,  # sj_scattering_direct_gdz
+    "9ee394180dbc2b72f6e97223a495365d2edd6151": 269992606,  # sj_scattering_direct_gzd
+    "5a989dd1e2cb1a35ab0e293efec0b8e8057569ac": 270298972,  # sj_scattering_direct_zdg
+    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 270137310,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
