@@ -16,6 +16,13 @@ or 134 MB, larger than the 256 MB last-level cache, so every step streams HBM.
 Printed: one JSON line (metric, value = algorithmic GB/s of the whole step,
 roofline of the dominant kernel from live HIP-event timing, the CPU oracle
 baseline on a bounded sample, and the generic-kernel comparison).
+
+Other workloads (--workload): batched (200,000 small products, HIP graph),
+bf16 (split-BF16 LTimes at Z=262144 G=64 D=128 NM=64), picker (learned picker
+against the exhaustive tuner), fused (LTimes then LPlusTimes in one pass),
+values (weights compiled into the kernel), scattering (scattering source over
+the six nestings), mass (tensor-product mass operator), copy (counter
+calibration).  Each prints one JSON line of the same form.
 """
 from __future__ import annotations
 
