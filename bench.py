@@ -77,12 +77,12 @@ MEASURED_TRAFFIC = {
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "7cf0defc5808a86711ab4fb004ef6de6e18a9152": 270840139,  # sj_scattering_direct_dgz
-    "503826a1ec572b26fc89963507493b01cb4fa9c7": 271240395,  # sj_scattering_direct_dzg
-    "89859078ba492326937d0ede52a949485b44fa27": 270903883,  # sj_scattering_direct_gdz
-    "9ee394180dbc2b72f6e97223a495365d2edd6151": 269992606,  # sj_scattering_direct_gzd
-    "5a989dd1e2cb1a35ab0e293efec0b8e8057569ac": 270298972,  # sj_scattering_direct_zdg
-    "e5ecc363391a365b5e5b542632b3bc42a8e3375a": 270137310,  # sj_scattering_direct_zgd
+    "497d6b5c474e096889a6cfc156fa4d584539ff3b": 270831746,  # sj_scattering_direct_dgz
+    "d732ad6ab0709509471e97d32ff8e7820445986b": 271030402,  # sj_scattering_direct_dzg
+    "da299dfc8c2163a2c5421f32007b52963cfed9f9": 270933313,  # sj_scattering_direct_gdz
+    "652a7c85aecdcc6c157d6ad403f9d6cc6e29d833": 270078627,  # sj_scattering_direct_gzd
+    "3be8255f70a12ecc4582d69e869b116d2474ca0f": 270951937,  # sj_scattering_direct_zdg
+    "8813c3f74488dea06f04da759f0e182d4fb0c1b7": 270060708,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }
@@ -788,6 +788,12 @@ def bench_scattering(a):
                         random_materials_us=round(tr * 1e3, 1), kernel=info["kernel_name"], vgprs=info["vgprs"],
                         compile_ms=round(info["compile_ms"], 1), src_sha1=source_sha1(P, P.SJ_SCATTERING, spec),
                         traffic=measured_traffic(P, P.SJ_SCATTERING, spec))
+        if lay == "ZDG":   # the other thread order of this nesting (order 2: threads along nm)
+            h2 = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat, order=2))
+            t2, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_reg, phi, out]), a.steps, stream)
+            t2r, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream)
+            res[lay]["threads_along_nm_us"] = round(t2 * 1e3, 1)
+            res[lay]["threads_along_nm_random_materials_us"] = round(t2r * 1e3, 1)
     dom = max(res, key=lambda k: res[k]["us"])
     line = {
         "metric": "scattering source GB/s over six nestings (specialized kernels)",

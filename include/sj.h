@@ -154,7 +154,15 @@ typedef struct sj_spec {
     int32_t  order;         /* DIRECT and FP64 MFMA columns: 0 = default, 1 = every workgroup walks the reduction (LTimes) or
                                output (LPlusTimes) rows in ascending order, 2 = each workgroup starts at a
                                different row group (rotation), which spreads concurrent accesses over
-                               DRAM channels when rows are megabytes apart */
+                               DRAM channels when rows are megabytes apart.
+                               FP64 MFMA rows (LTimes, LPlusTimes and the fused pair): 1 = each lane
+                               reads its operand rows from HBM, 2 = a group's rows move as flat runs
+                               through LDS (even D and NM); 0 = 2 where it fits.
+                               SJ_SCATTERING in the ZDG nesting: 0 or 1 = threads run along z (whole
+                               wave on one moment: one matrix per wave where zones of a material are
+                               contiguous), 2 = threads run along nm (several degrees per wave, the
+                               material's matrices staged in LDS: faster when the material changes from
+                               zone to zone); the other nestings accept 0, 1 or 2 and ignore it */
     int64_t  rows, inputs, width;  /* MLP: batch rows, input features, hidden width */
 } sj_spec;
 

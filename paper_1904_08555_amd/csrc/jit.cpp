@@ -469,8 +469,8 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (s->G > 64) return fail(SJ_ERR_UNSUPPORTED, "scattering keeps a line's G values in registers: G <= 64");
         if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
             return fail(SJ_ERR_UNSUPPORTED, "scattering has the DIRECT structure only");
-        if (s->tile_n != 0 || s->tile_k != 0 || s->unroll != 0 || (s->order != 0 && s->order != 1))
-            return fail(SJ_ERR_INVALID_ARG, "scattering takes no tiles");
+        if (s->tile_n != 0 || s->tile_k != 0 || s->unroll != 0 || s->order < 0 || s->order > 2)
+            return fail(SJ_ERR_INVALID_ARG, "scattering takes no tiles; order 0, 1 or 2");
         if (s->flags & SJ_FLAG_ACCUMULATE) return fail(SJ_ERR_INVALID_ARG, "scattering overwrites its output");
         const int64_t lines = s->NM * s->Z;
         if (lines > (int64_t(1) << 40) || s->G * lines > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "array size overflows");
@@ -495,20 +495,28 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         default: sz = Gv * NMv; sg = NMv; snm = 1; break;
         }
         const bool run_lines = (sg == 1 && std::min(snm, sz) == Gv);
-        const bool slds = (snm < sz && nl * (Gv * Gv + 2) * 8 <= 64 * 1024);
+        // lanes along nm only where nm is the faster axis and g is not innermost, or on request
+        // (order 2) in ZDG; measured on MI355X at Z=32768 G=32 NM=16 with four materials in zone
+        // regions, ZDG with lanes along z 89.6 us against 103.5 us along nm; with a material drawn
+        // per zone, 351 us against 218 us
+        const bool zdg_nm = (sg == 1 && snm < sz && s->order == 2);
+        const bool lane_nm = (snm < sz) && (sg != 1 || zdg_nm);
+        const bool slds = (lane_nm && nl * (Gv * Gv + 2) * 8 <= 64 * 1024);
         const int64_t tp = Gv + (Gv % 2 == 0 ? 2 : 1);
         auto lds = [&](int block) {
             return (run_lines ? (int64_t)(block / 64) * 64 * tp * 8 : 0) + (slds ? nl * (Gv * Gv + 2) * 8 + 8 : 0);
         };
-        // measured on MI355X at Z=32768 G=32 NM=16: ZDG (line tiles and staged matrices) 102.7 us at
-        // 384 threads against 116.9 us at 256; 256 for the other nestings
+        // measured on MI355X at Z=32768 G=32 NM=16: line tiles and staged matrices (ZDG, lanes along
+        // nm) 102.7 us at 384 threads against 116.9 us at 256; line tiles alone (DZG, ZDG) 74.0 and
+        // 89.6 us at 64 threads against 76.8 and 92.2 us at 256; 256 for the other nestings
         // (512 bytes kept back for the compiler's alignment of the shared arrays)
-        key.block = s->block ? s->block : ((run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : 256);
+        key.block = s->block ? s->block
+                             : (run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : (run_lines && !slds) ? 64 : 256;
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
         if (lds(key.block) + 512 > 160 * 1024)
             return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
         key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
-        key.order = 1;
+        key.order = zdg_nm ? 2 : 1;
         return (*out = key), SJ_OK;
     }
     if (k == SJ_MLP_FWD || k == SJ_MLP_BWD || k == SJ_ADAM) {
@@ -745,14 +753,15 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         int64_t nl = 0;
         while ((nl + 1) * (nl + 1) <= NM - 1) ++nl;
         nl += 1;
+        const bool lane_nm = (snm < sz) && (sg != 1 || k.order == 2);   // as in the key
         int ntl = 1, nts = 1;   // phi is read once and phi_out written once: streamed
         if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
         if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
         o << "#define SJ_NM " << NM << "\n#define SJ_G " << G << "\n#define SJ_Z " << Z << sfx << "\n#define SJ_NMAT "
           << k.rows << "\n#define SJ_NL " << nl << "\n#define SJ_SNM " << snm << sfx << "\n#define SJ_SG " << sg << sfx
-          << "\n#define SJ_SZ " << sz << sfx << "\n#define SJ_LANE_NM " << (snm < sz ? 1 : 0) << "\n#define SJ_RUN_LINES "
+          << "\n#define SJ_SZ " << sz << sfx << "\n#define SJ_LANE_NM " << (lane_nm ? 1 : 0) << "\n#define SJ_RUN_LINES "
           << ((sg == 1 && std::min(snm, sz) == G) ? 1 : 0) << "\n#define SJ_SLDS "
-          << ((snm < sz && nl * (G * G + 2) * 8 <= 64 * 1024) ? 1 : 0) << "\n#define SJ_BLOCK "
+          << ((lane_nm && nl * (G * G + 2) * 8 <= 64 * 1024) ? 1 : 0) << "\n#define SJ_BLOCK "
           << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n";
         body = kTpl_scattering_direct;
         static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};

@@ -373,11 +373,21 @@ def test_scattering_specs(P):
     src = P.sj_emit_source(P.SJ_SCATTERING, **base)
     assert "#define SJ_NL 3" in src and "#define SJ_LANE_NM 1" in src and "#define SJ_SG 9" in src
     assert "#define SJ_LANE_NM 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(base, layout="DGZ"))
+    # ZDG: threads along z by default, along nm (staged degree matrices) with order 2
+    zdg = dict(base, layout="ZDG", flags=0)
+    src = P.sj_emit_source(P.SJ_SCATTERING, **zdg)
+    assert "#define SJ_LANE_NM 0" in src and "#define SJ_SLDS 0" in src and "#define SJ_RUN_LINES 1" in src
+    src = P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, order=2))
+    assert "#define SJ_LANE_NM 1" in src and "#define SJ_SLDS 1" in src and "#define SJ_RUN_LINES 1" in src
+    assert P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co)) != P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co, order=2))
+    # order only changes ZDG: elsewhere 0, 1 and 2 give the same key
+    assert len({P.sj_specialize(P.SJ_SCATTERING, **dict(base, order=o)) for o in (0, 1, 2)}) == 1
     for bad, status in ((dict(count=0), P.SJ_ERR_INVALID_ARG), (dict(G=65), P.SJ_ERR_UNSUPPORTED),
                         (dict(variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED), (dict(tile_n=2), P.SJ_ERR_INVALID_ARG),
                         (dict(flags=co | P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG), (dict(dtype=P.SJ_BF16), P.SJ_ERR_INVALID_ARG),
                         (dict(layout=7), P.SJ_ERR_INVALID_ARG),
-                        (dict(layout="ZDG", Z=32768, G=32, NM=16, count=4, block=512), P.SJ_ERR_UNSUPPORTED)):
+                        (dict(order=3), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZDG", Z=32768, G=32, NM=16, count=4, block=512, order=2), P.SJ_ERR_UNSUPPORTED)):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_SCATTERING, **dict(base, **bad))
         assert e.value.status == status, bad

@@ -37,9 +37,9 @@ def scat_inputs(seed, Z, G, NM, nmat, regions):
     return S, mat, phi
 
 
-def run(P, layout, Z, G, NM, nmat, S, mat, phi_flat):
+def run(P, layout, Z, G, NM, nmat, S, mat, phi_flat, order=0):
     out = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
-    h = P.sj_specialize(P.SJ_SCATTERING, layout=layout, Z=Z, G=G, NM=NM, count=nmat)
+    h = P.sj_specialize(P.SJ_SCATTERING, layout=layout, Z=Z, G=G, NM=NM, count=nmat, order=order)
     P.sj_run(h, [dev(S.ravel()), dev(mat), dev(phi_flat), out])
     return host(out)
 
@@ -56,6 +56,21 @@ def test_scattering_parity(P, orc, layout, shape, regions):
     ref = orc.scattering(layout, Z, G, NM, S, mat, phi_flat)
     scale = orc.scattering(layout, Z, G, NM, S, mat, phi_flat, absolute=True)
     assert componentwise_err(got, ref, scale) <= TOL_F64
+
+
+@pytest.mark.parametrize("shape", [(37, 5, 10, 3), (300, 3, 16, 2), (1, 1, 1, 1), (256, 32, 16, 4), (9, 4, 40, 2)],
+                         ids=lambda s: "Z%dG%dNM%dmat%d" % s)
+@pytest.mark.parametrize("regions", [True, False], ids=["regions", "random"])
+def test_scattering_parity_zdg_threads_along_nm(P, orc, shape, regions):
+    """ZDG with order 2: threads along nm, the material's degree matrices staged in LDS."""
+    Z, G, NM, nmat = shape
+    S, mat, phi = scat_inputs(47, Z, G, NM, nmat, regions)
+    phi_flat = gen.to_layout(phi, "ZDG").ravel()
+    got = run(P, "ZDG", Z, G, NM, nmat, S, mat, phi_flat, order=2)
+    ref = orc.scattering("ZDG", Z, G, NM, S, mat, phi_flat)
+    scale = orc.scattering("ZDG", Z, G, NM, S, mat, phi_flat, absolute=True)
+    assert componentwise_err(got, ref, scale) <= TOL_F64
+    assert np.array_equal(got, run(P, "ZDG", Z, G, NM, nmat, S, mat, phi_flat, order=1))   # same sums, same order
 
 
 @pytest.mark.parametrize("layout", ["DGZ", "GZD", "ZDG"])
@@ -96,8 +111,8 @@ def test_scattering_checks(P):
     assert e.value.status == P.SJ_ERR_ALIAS
 
 
-@pytest.mark.parametrize("layout", ["DGZ", "ZGD", "ZDG"])
-def test_scattering_full_size_sampled(P, orc, layout):
+@pytest.mark.parametrize("layout,order", [("DGZ", 0), ("ZGD", 0), ("ZDG", 0), ("ZDG", 2), ("DZG", 0)])
+def test_scattering_full_size_sampled(P, orc, layout, order):
     """Z=32768 G=32 NM=16, four materials in contiguous zone regions: 512
     sampled zones (all their lines) against the oracle on those zones."""
     Z, G, NM, nmat = 32768, 32, 16, 4
@@ -108,7 +123,7 @@ def test_scattering_full_size_sampled(P, orc, layout):
     from sj_inputs import device as gdev
     gdev.fill(phi_d, 0, gen.ARR_PHI, gdev.DIST_U01, li, (NM, G, Z))
     out = torch.empty_like(phi_d)
-    h = P.sj_specialize(P.SJ_SCATTERING, layout=layout, Z=Z, G=G, NM=NM, count=nmat)
+    h = P.sj_specialize(P.SJ_SCATTERING, layout=layout, Z=Z, G=G, NM=NM, count=nmat, order=order)
     P.sj_run(h, [dev(S.ravel()), dev(mat), phi_d, out])
     zs = np.sort(np.random.default_rng(45).choice(Z, 512, replace=False))
     zs[-1] = Z - 1
