@@ -77,12 +77,12 @@ MEASURED_TRAFFIC = {
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "497d6b5c474e096889a6cfc156fa4d584539ff3b": 270831746,  # sj_scattering_direct_dgz
-    "d732ad6ab0709509471e97d32ff8e7820445986b": 271030402,  # sj_scattering_direct_dzg
-    "da299dfc8c2163a2c5421f32007b52963cfed9f9": 270933313,  # sj_scattering_direct_gdz
-    "652a7c85aecdcc6c157d6ad403f9d6cc6e29d833": 270078627,  # sj_scattering_direct_gzd
-    "3be8255f70a12ecc4582d69e869b116d2474ca0f": 270951937,  # sj_scattering_direct_zdg
-    "8813c3f74488dea06f04da759f0e182d4fb0c1b7": 270060708,  # sj_scattering_direct_zgd
+    "8831dfda1d640ff6f6e915f34ef7dcc9012e4a74": 270831220,  # sj_scattering_direct_dgz
+    "4a8fcfd377eca19a8f6184167d06480d73b466d0": 271512933,  # sj_scattering_direct_dzg
+    "ca7550fb3403e250c826195f3b688d9fd300b39e": 271087988,  # sj_scattering_direct_gdz
+    "b5fd3dc8ac220bbf013520c53d0366b25de595d2": 270028948,  # sj_scattering_direct_gzd
+    "a2e38850112c83b81b530c7b4bc59ce162bdae47": 271258408,  # sj_scattering_direct_zdg
+    "9ed34b8b4be3bca6cd3f545ab92db599b7fd54e3": 270099861,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }

@@ -507,11 +507,11 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             return (run_lines ? (int64_t)(block / 64) * 64 * tp * 8 : 0) + (slds ? nl * (Gv * Gv + 2) * 8 + 8 : 0);
         };
         // measured on MI355X at Z=32768 G=32 NM=16: line tiles and staged matrices (ZDG, lanes along
-        // nm) 102.7 us at 384 threads against 116.9 us at 256; line tiles alone (DZG, ZDG) 74.0 and
-        // 89.6 us at 64 threads against 76.8 and 92.2 us at 256; 256 for the other nestings
-        // (512 bytes kept back for the compiler's alignment of the shared arrays)
+        // nm) 102.7 us at 384 threads against 116.9 us at 256; persistent line tiles alone (DZG, ZDG)
+        // 66.9 and 77.7 us at 128 threads, 65.3 and 80.9 us at 256, 71.0 and 83.3 us at 64; 256 for
+        // the other nestings (512 bytes kept back for the compiler's alignment of the shared arrays)
         key.block = s->block ? s->block
-                             : (run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : (run_lines && !slds) ? 64 : 256;
+                             : (run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : (run_lines && !slds) ? 128 : 256;
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
         if (lds(key.block) + 512 > 160 * 1024)
             return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
@@ -577,12 +577,28 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
 }
 
+// scattering with G innermost and no staged matrices (threads along z): persistent waves that
+// load their next 64 lines during the current ones (measured on MI355X at Z=32768 G=32 NM=16,
+// zone regions: DZG 66.9 us against 73.7 us, ZDG 77.7 us against 89.2 us, bit-identical)
+static bool scattering_persistent(const SpecKey &k)
+{
+    const bool sg1 = (k.layout == SJ_DZG || k.layout == SJ_ZDG);
+    return sg1 && k.order != 2;
+}
+
 Geometry key_geometry(const SpecKey &k)
 {
     Geometry g{0, (unsigned)k.block, 0};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
-    if (k.kernel == SJ_SCATTERING) g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
+    if (k.kernel == SJ_SCATTERING) {
+        g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
+        if (scattering_persistent(k)) {
+            const int64_t groups = (k.NM * k.Z + 63) / 64, waves = k.block / 64;
+            g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
+            g.persistent = 1;
+        }
+    }
     if (k.kernel == SJ_MASS) {
         const int64_t per_block = (int64_t)(k.block / 64) * k.tile_n;
         g.grid = (unsigned)((k.rows + per_block - 1) / per_block);
@@ -754,6 +770,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         while ((nl + 1) * (nl + 1) <= NM - 1) ++nl;
         nl += 1;
         const bool lane_nm = (snm < sz) && (sg != 1 || k.order == 2);   // as in the key
+        o << "#define SJ_PERSIST " << (scattering_persistent(k) ? 1 : 0) << "\n";
         int ntl = 1, nts = 1;   // phi is read once and phi_out written once: streamed
         if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
         if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;

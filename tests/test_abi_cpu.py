@@ -377,8 +377,12 @@ def test_scattering_specs(P):
     zdg = dict(base, layout="ZDG", flags=0)
     src = P.sj_emit_source(P.SJ_SCATTERING, **zdg)
     assert "#define SJ_LANE_NM 0" in src and "#define SJ_SLDS 0" in src and "#define SJ_RUN_LINES 1" in src
+    assert "#define SJ_PERSIST 1" in src   # persistent waves prefetching their next 64 lines
     src = P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, order=2))
     assert "#define SJ_LANE_NM 1" in src and "#define SJ_SLDS 1" in src and "#define SJ_RUN_LINES 1" in src
+    assert "#define SJ_PERSIST 0" in src   # workgroup barriers of the staged matrices: not persistent
+    assert "#define SJ_PERSIST 1" in P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, layout="DZG"))
+    assert "#define SJ_PERSIST 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, layout="DGZ"))
     assert P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co)) != P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co, order=2))
     # order only changes ZDG: elsewhere 0, 1 and 2 give the same key
     assert len({P.sj_specialize(P.SJ_SCATTERING, **dict(base, order=o)) for o in (0, 1, 2)}) == 1
