@@ -77,12 +77,12 @@ MEASURED_TRAFFIC = {
     "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
     "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
     "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "8831dfda1d640ff6f6e915f34ef7dcc9012e4a74": 270831220,  # sj_scattering_direct_dgz
-    "4a8fcfd377eca19a8f6184167d06480d73b466d0": 271512933,  # sj_scattering_direct_dzg
-    "ca7550fb3403e250c826195f3b688d9fd300b39e": 271087988,  # sj_scattering_direct_gdz
-    "b5fd3dc8ac220bbf013520c53d0366b25de595d2": 270028948,  # sj_scattering_direct_gzd
-    "a2e38850112c83b81b530c7b4bc59ce162bdae47": 271258408,  # sj_scattering_direct_zdg
-    "9ed34b8b4be3bca6cd3f545ab92db599b7fd54e3": 270099861,  # sj_scattering_direct_zgd
+    "e120e93ca86b864e241fff0aa89efe2e4319e291": 270830453,  # sj_scattering_direct_dgz
+    "4e2c3ac84a7f2b325fb8fc8e47541b8ee6cec3e7": 271573028,  # sj_scattering_direct_dzg
+    "52cb2358ddd2f1a46a9680477c17eef9ccfcaa09": 271022197,  # sj_scattering_direct_gdz
+    "4d2b73c740ba615ace95af5f2ede020de2505f14": 270267094,  # sj_scattering_direct_gzd
+    "312fabfc2ba62328ebd0a8aa49e65a69c7e91586": 271223274,  # sj_scattering_direct_zdg
+    "b1f109944946633eeb6ab6f0890ffd3612cebb81": 269936663,  # sj_scattering_direct_zgd
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
 }

@@ -508,10 +508,15 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         };
         // measured on MI355X at Z=32768 G=32 NM=16: line tiles and staged matrices (ZDG, lanes along
         // nm) 102.7 us at 384 threads against 116.9 us at 256; persistent line tiles alone (DZG, ZDG)
-        // 66.9 and 77.7 us at 128 threads, 65.3 and 80.9 us at 256, 71.0 and 83.3 us at 64; 256 for
-        // the other nestings (512 bytes kept back for the compiler's alignment of the shared arrays)
+        // 66.9 and 77.7 us at 128 threads, 65.3 and 80.9 us at 256, 71.0 and 83.3 us at 64; staged
+        // matrices with two zones per thread (GZD, ZGD) 60.6 and 60.0 us at 512 threads, 74.6 and
+        // 74.8 us at 256 (the staging is shared by twice the zones); 256 for the other nestings
+        // (512 bytes kept back for the compiler's alignment of the shared arrays)
         key.block = s->block ? s->block
-                             : (run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384 : (run_lines && !slds) ? 128 : 256;
+                             : (run_lines && slds && lds(384) + 512 <= 160 * 1024) ? 384
+                             : (run_lines && !slds)                                ? 128
+                             : (!run_lines && slds)                                ? 512
+                                                                                   : 256;
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
         if (lds(key.block) + 512 > 160 * 1024)
             return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
@@ -577,6 +582,18 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
 }
 
+// scattering with threads along nm, g not innermost and the degree matrices staged in LDS:
+// two zones per thread (measured on MI355X at Z=32768 G=32 NM=16, zone regions, 512-thread
+// workgroups: GZD 60.6 us against 65.0 us, ZGD 60.0 us against 71.3 us, bit-identical)
+static bool scattering_pairs(const SpecKey &k)
+{
+    const bool nm_fastest = (k.layout == SJ_GZD || k.layout == SJ_ZGD);
+    int64_t nl = 0;
+    while ((nl + 1) * (nl + 1) <= k.NM - 1) ++nl;
+    nl += 1;
+    return nm_fastest && nl * (k.G * k.G + 2) * 8 <= 64 * 1024;
+}
+
 // scattering with G innermost and no staged matrices (threads along z): persistent waves that
 // load their next 64 lines during the current ones (measured on MI355X at Z=32768 G=32 NM=16,
 // zone regions: DZG 66.9 us against 73.7 us, ZDG 77.7 us against 89.2 us, bit-identical)
@@ -593,6 +610,7 @@ Geometry key_geometry(const SpecKey &k)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
     if (k.kernel == SJ_SCATTERING) {
         g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
+        if (scattering_pairs(k)) g.grid = (unsigned)((k.NM * ((k.Z + 1) / 2) + k.block - 1) / k.block);
         if (scattering_persistent(k)) {
             const int64_t groups = (k.NM * k.Z + 63) / 64, waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
@@ -770,7 +788,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         while ((nl + 1) * (nl + 1) <= NM - 1) ++nl;
         nl += 1;
         const bool lane_nm = (snm < sz) && (sg != 1 || k.order == 2);   // as in the key
-        o << "#define SJ_PERSIST " << (scattering_persistent(k) ? 1 : 0) << "\n";
+        o << "#define SJ_PERSIST " << (scattering_persistent(k) ? 1 : 0) << "\n#define SJ_PAIR "
+          << (scattering_pairs(k) ? 1 : 0) << "\n";
         int ntl = 1, nts = 1;   // phi is read once and phi_out written once: streamed
         if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
         if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;

@@ -383,6 +383,9 @@ def test_scattering_specs(P):
     assert "#define SJ_PERSIST 0" in src   # workgroup barriers of the staged matrices: not persistent
     assert "#define SJ_PERSIST 1" in P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, layout="DZG"))
     assert "#define SJ_PERSIST 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, layout="DGZ"))
+    # nm fastest with staged degree matrices: two zones per thread
+    for lay, pair in (("GZD", 1), ("ZGD", 1), ("DGZ", 0), ("ZDG", 0)):
+        assert ("#define SJ_PAIR %d" % pair) in P.sj_emit_source(P.SJ_SCATTERING, **dict(zdg, layout=lay)), lay
     assert P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co)) != P.sj_specialize(P.SJ_SCATTERING, **dict(zdg, flags=co, order=2))
     # order only changes ZDG: elsewhere 0, 1 and 2 give the same key
     assert len({P.sj_specialize(P.SJ_SCATTERING, **dict(base, order=o)) for o in (0, 1, 2)}) == 1
