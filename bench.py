@@ -63,6 +63,11 @@ MEASURED_TRAFFIC = {
     "385b9213b1c196f5763daab7b57762938b92611d": 939708156,  # sj_ltimes_rows_mfma_lds_zgd
     "c524a2bbfc0f9a1e5e68eb37e59b080356775bee": 939764733,  # sj_lplustimes_rows_mfma_zgd
     "456ff6bccbb93f1b5b963602531428289040ee2d": 940383099,  # sj_lplustimes_cols_mfma_zdg (unroll 2)
+    # other winners of the tuning on other boxes (LTimes DGZ tile 2 unroll 8, DZG tile 2 unroll 16
+    # block 512 order 2, LPlusTimes ZDG direct unroll 8 block 512)
+    "21b517bf80987334c6518ddecdb0091fd0dd45ce": 939787834,  # sj_ltimes_direct_dgz
+    "11ab1f5d02c74da13a3374820380f266957586a9": 939813114,  # sj_ltimes_direct_dzg
+    "dd8ff4aabde3ef06e5e21b8913d94f04cef11817": 940570423,  # sj_lplustimes_direct_zdg
     # fused LTimes + LPlusTimes (phi written too), scattering (4 materials in zone regions),
     # mass operator, BF16 LTimes: the default specializations of their workloads
     "08de64ddce1c10477dfd9fb1f82c56008bd3d5f1": 1746069941,  # sj_ltimes_lplus_direct_dgz
