@@ -5,8 +5,7 @@ baseline leg may import this package; the product library never does.
 
 ``build()`` compiles ``oracle.c`` with gcc (-O2 -ffp-contract=off -fopenmp)
 into ``liboracle.so`` next to this file.  The wrappers below take numpy arrays
-and call the C functions unchanged; they hold no arithmetic of their own except
-``quadrature`` helpers in :mod:`oracle.quadrature`.
+and call the C functions unchanged; they hold no arithmetic of their own.
 """
 from __future__ import annotations
 

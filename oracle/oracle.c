@@ -51,6 +51,7 @@
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -217,14 +218,14 @@ static int orc_mass_impl(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, cons
     if (dim < 1 || dim > 3 || D1D < 1 || Q1D < 1) return -1;
     int64_t nd = 1, nq = 1;
     for (int64_t k = 0; k < dim; ++k) { nd *= D1D; nq *= Q1D; }
-#pragma omp parallel for schedule(static)
+    int failed = 0;
+#pragma omp parallel for schedule(static) reduction(|| : failed)
     for (int64_t e = 0; e < NE; ++e) {
         const double *x = X + e * nd;
         const double *dq = Dq + e * nq;
         double *y = Y + e * nd;
-        double u_stack[4096];
-        double *u = u_stack;
-        if (nq > 4096) continue;   /* the oracle serves small elements only */
+        double *u = (double *)malloc((size_t)nq * sizeof(double));   /* B x_e scaled by D_e, one value per point */
+        if (!u) { failed = 1; continue; }
         for (int64_t q = 0; q < nq; ++q) {
             double acc = 0.0;
             for (int64_t j = 0; j < nd; ++j) acc = acc + orc_basis(B1, dim, D1D, Q1D, q, j, absolute) * (absolute ? fabs(x[j]) : x[j]);
@@ -235,8 +236,9 @@ static int orc_mass_impl(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, cons
             for (int64_t q = 0; q < nq; ++q) acc = acc + orc_basis(B1, dim, D1D, Q1D, q, i, absolute) * u[q];
             y[i] = acc;
         }
+        free(u);
     }
-    return nq > 4096 ? -2 : 0;
+    return failed ? -2 : 0;
 }
 
 int orc_mass(int64_t dim, int64_t D1D, int64_t Q1D, int64_t NE, const double *B1, const double *Dq, const double *X,

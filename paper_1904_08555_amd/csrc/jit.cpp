@@ -533,6 +533,10 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             if (s->width < 1 || s->width > 128) return fail(SJ_ERR_INVALID_ARG, "width must be in [1, 128]");
             if (mlp_nparams(s->inputs, s->width) * 4 > 64 * 1024)
                 return fail(SJ_ERR_UNSUPPORTED, "MLP parameters exceed 64 KiB of LDS");
+            // the kernels index the rows * (4 width + 2) workspace and the rows * inputs
+            // features with 32-bit offsets
+            if (s->rows * (4 * s->width + 2) >= (int64_t(1) << 31) || s->rows * s->inputs >= (int64_t(1) << 31))
+                return fail(SJ_ERR_INVALID_ARG, "rows * (4 width + 2) and rows * inputs must be below 2^31");
             key.inputs = s->inputs;
             key.width = s->width;
         }

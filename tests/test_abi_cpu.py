@@ -199,6 +199,34 @@ def test_bgemm_mlp_invalid_specs(P, kernel, bad):
     assert e.value.status in (P.SJ_ERR_INVALID_ARG, P.SJ_ERR_UNSUPPORTED)
 
 
+def test_mlp_workspace_offsets_fit_32_bits(P):
+    """The MLP kernels index their rows * (4 width + 2) workspace with 32-bit
+    offsets: a shape that would wrap is refused before any compile; the largest
+    accepted row count at width 64 still fits."""
+    width = 64
+    limit = (1 << 31) // (4 * width + 2)          # rows * 258 < 2^31  <=>  rows <= limit (2^31 is not a multiple)
+    for k in (P.SJ_MLP_FWD, P.SJ_MLP_BWD):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(k, dtype=P.SJ_F32, rows=limit + 1, inputs=24, width=width, flags=P.SJ_FLAG_COMPILE_ONLY)
+        assert e.value.status == P.SJ_ERR_INVALID_ARG and "2^31" in str(e.value)
+    assert limit * (4 * width + 2) < (1 << 31) <= (limit + 1) * (4 * width + 2)
+    src = P.sj_emit_source(P.SJ_MLP_BWD, dtype=P.SJ_F32, rows=limit, inputs=24, width=width)
+    assert f"#define SJ_R {limit}" in src
+
+
+def test_mass_accepted_range(P):
+    """D1D and Q1D in [1, 32]; for dim 3 the per-wave LDS tiles of one element,
+    (2 max(D1D, Q1D)^3 + Q1D^3) doubles, must fit 160 KiB: 18 fits, 19 does not."""
+    for dim, n in ((1, 32), (2, 32), (3, 18)):
+        P.sj_emit_source(P.SJ_MASS, D=n, NM=n, inputs=dim, count=3)
+    with pytest.raises(P.SJError) as e:
+        P.sj_emit_source(P.SJ_MASS, D=19, NM=19, inputs=3, count=3)
+    assert e.value.status == P.SJ_ERR_UNSUPPORTED
+    with pytest.raises(P.SJError) as e:
+        P.sj_emit_source(P.SJ_MASS, D=33, NM=4, inputs=1, count=3)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+
+
 def test_compile_farm_matches_local_compile(P):
     """Worker processes produce the same code object the parent compiles."""
     from paper_1904_08555_amd import farm

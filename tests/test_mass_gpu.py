@@ -99,3 +99,17 @@ def test_mass_full_size_sampled(P, orc):
     assert componentwise_err(got, ref, scale) <= TOL_F64
     del Dq_d, X_d, Y_d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("shape", [(1, 32, 32, 37), (2, 32, 32, 5), (2, 32, 1, 9), (2, 1, 32, 9), (3, 18, 18, 2),
+                                   (3, 16, 18, 3)],
+                         ids=lambda s: "dim%dD%dQ%dNE%d" % s)
+def test_mass_parity_range_edges(P, orc, shape):
+    """The largest sizes the specializer accepts: D1D = Q1D = 32 for dim 1 and 2,
+    and D1D = Q1D = 18 for dim 3 (one element's LDS tiles fill 160 KiB at 18)."""
+    dim, D1D, Q1D, NE = shape
+    B1, Dq, X = inputs(64, dim, D1D, Q1D, NE)
+    got = run(P, dim, D1D, Q1D, NE, B1, Dq, X)
+    ref = orc.mass(dim, D1D, Q1D, B1, Dq, X)
+    scale = orc.mass(dim, D1D, Q1D, B1, Dq, X, absolute=True)
+    assert componentwise_err(got, ref, scale) <= TOL_F64

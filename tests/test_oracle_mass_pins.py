@@ -108,3 +108,32 @@ def test_mass_symmetric(orc):
     a = float(np.dot(orc.mass(dim, D1D, Q1D, B1, Dq, x1), x2))
     b = float(np.dot(x1, orc.mass(dim, D1D, Q1D, B1, Dq, x2)))
     assert abs(a - b) <= 1e-13 * (abs(a) + abs(b) + 1.0)
+
+
+@pytest.mark.parametrize("dim,D1D,Q1D", [(1, 5, 7), (2, 4, 6), (3, 3, 5)])
+def test_mass_absscale_kronecker(orc, dim, D1D, Q1D):
+    """The error scale every mass parity bar divides by,
+    |B|^T diag(|D_e|) |B| |x_e| with |B| = |kron(B1, ..)|, built with numpy; B1, D
+    and x all signed, so a scale that drops an absolute value or doubles a factor
+    fails.  All terms are nonnegative: the two orders agree to 2 gamma_n relative."""
+    rng = np.random.default_rng(56)
+    NE = 5
+    B1 = rng.uniform(-1, 1, (Q1D, D1D))
+    Dq = rng.uniform(-1, 1, (NE, Q1D ** dim))
+    X = rng.uniform(-1, 1, (NE, D1D ** dim))
+    Ba = np.abs(kron_matrix(dim, B1))
+    ref = np.stack([Ba.T @ (np.abs(Dq[e]) * (Ba @ np.abs(X[e]))) for e in range(NE)])
+    got = orc.mass(dim, D1D, Q1D, B1, Dq, X, absolute=True).reshape(NE, -1)
+    n = D1D ** dim + Q1D ** dim + 2 * dim + 2
+    assert np.all(ref > 0)
+    assert np.all(np.abs(got - ref) <= 2 * n * U / (1 - n * U) * ref)
+
+
+def test_mass_large_element_supported(orc):
+    """Elements with more than 4096 points (dim 3, Q1D = 17) are computed, not
+    skipped: with B1 = I the operator is y = D * x exactly."""
+    dim, D1D, NE = 3, 17, 2
+    rng = np.random.default_rng(57)
+    Dq = rng.uniform(-2, 2, NE * D1D ** dim)
+    X = rng.uniform(-2, 2, NE * D1D ** dim)
+    assert np.array_equal(orc.mass(dim, D1D, D1D, np.eye(D1D), Dq, X), Dq * X)

@@ -302,6 +302,57 @@ def test_bf16_emulation_bounds(orc):
     assert e1.max() < e0.max() / 20
 
 
+def bf16_exact(x: Fraction) -> Fraction:
+    """Nearest value with 8 significant bits, ties to even, on rationals: the
+    definition of round-to-nearest-even bfloat16 for normal results."""
+    if x == 0:
+        return Fraction(0)
+    s = -1 if x < 0 else 1
+    a = abs(x)
+    e = 0
+    while a >= 2 ** e:
+        e += 1
+    while a < 2 ** (e - 1):
+        e -= 1
+    # 2^(e-1) <= a < 2^e: keep 8 bits, i.e. a multiple of 2^(e-8)
+    r = round(a * Fraction(2) ** (8 - e))      # Fraction.__round__ rounds ties to even
+    return s * r * Fraction(2) ** (e - 8)
+
+
+@pytest.mark.parametrize("layout", ["DGZ", "GZD", "ZDG"])
+def test_bf16_emulation_exact_split(orc, layout):
+    """The split emulation against exact rational arithmetic at a tiny shape:
+    hi = RNE_bf16(x), lo = RNE_bf16(x - hi) formed on rationals, every product
+    and the sum exact; the oracle (FP64 products and sums) must be within
+    gamma_{3D} * sum |terms| of it.  Inputs are not bf16 values, so lo != 0 and
+    an unrounded or dropped lo, or a dropped cross term, fails."""
+    Z, G, D, NM = 3, 2, 6, 4
+    psi, L, _ = logical_inputs(9, D, G, Z, NM)
+    for v in np.concatenate([L.ravel(), psi.ravel()]):
+        assert Fraction(float(orc.bf16_round(float(v)))) == bf16_exact(Fraction(float(v)))
+
+    def split(v):
+        h = bf16_exact(Fraction(float(v)))
+        return h, bf16_exact(Fraction(float(v)) - h)
+    Ls = [[split(L[nm, d]) for d in range(D)] for nm in range(NM)]
+    for mode in (0, 1):
+        got = gen.from_layout(orc.ltimes_bf16_emul(mode, layout, Z, G, D, NM, L, gen.to_layout(psi, layout)),
+                              layout, NM, G, Z)
+        for g, z in itertools.product(range(G), range(Z)):
+            ps = [split(psi[d, g, z]) for d in range(D)]
+            assert any(lo != 0 for _, lo in ps)
+            for nm in range(NM):
+                terms = []
+                for d in range(D):
+                    (lh, ll), (ph, pl) = Ls[nm][d], ps[d]
+                    terms.append(lh * ph)
+                    if mode == 1:
+                        terms += [lh * pl, ll * ph]
+                ex = sum(terms, Fraction(0))
+                bound = Fraction(gamma(3 * D)) * sum(abs(t) for t in terms)
+                assert abs(Fraction(float(got[nm, g, z])) - ex) <= bound
+
+
 # --------------------------------------------------------------------- MLP
 
 

@@ -125,3 +125,39 @@ def test_scattering_rejects_bad_material(orc):
     Z, G, NM = 3, 2, 4
     with pytest.raises(ValueError):
         orc.scattering("DGZ", Z, G, NM, np.ones((1, 2, G, G)), np.array([0, 1, 0], np.int32), np.zeros(NM * G * Z))
+
+
+def absscale_reference(S, mat, phi):
+    """sum_g' |S[mat(z)][n(nm)][g][g']| |phi[nm,g',z]| built with numpy's einsum
+    from the degree table and the material map (logical [NM][G][Z])."""
+    deg = np.array(degrees(phi.shape[0]))
+    Sz = np.abs(S)[mat][:, deg]                    # [Z][NM][G][G'] of the zone's material and moment's degree
+    return np.einsum("znab,nbz->naz", Sz, np.abs(phi))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_scattering_absscale_independent(orc, layout):
+    """The error scale that every scattering parity bar divides by, against an
+    independent einsum over |S| and |phi| (terms are nonnegative, so two
+    summation orders differ by at most 2 gamma_G relative); signed S and phi,
+    so a scale that drops an absolute value or counts a factor twice fails."""
+    Z, G, NM, nmat = 7, 5, 10, 3
+    S, mat, phi = inputs(37, Z, G, NM, nmat)
+    got = gen.from_layout(orc.scattering(layout, Z, G, NM, S, mat, gen.to_layout(phi, layout), absolute=True),
+                          layout, NM, G, Z)
+    ref = absscale_reference(S, mat, phi)
+    gam = G * U / (1 - G * U)
+    assert np.all(np.abs(got - ref) <= 2 * gam * ref)
+
+
+def test_scattering_absscale_exact_rational(orc):
+    """The scale at a tiny shape equals the exact rational sum of |S||phi| to gamma_G."""
+    Z, G, NM, nmat = 3, 3, 5, 2
+    S, mat, phi = inputs(38, Z, G, NM, nmat)
+    got = gen.from_layout(orc.scattering("ZGD", Z, G, NM, S, mat, gen.to_layout(phi, "ZGD"), absolute=True),
+                          "ZGD", NM, G, Z)
+    ex = brute(np.abs(S), mat, np.abs(phi))
+    gam = G * U / (1 - G * U)
+    for idx in itertools.product(range(NM), range(G), range(Z)):
+        assert ex[idx] > 0
+        assert abs(Fraction(float(got[idx])) - ex[idx]) <= Fraction(gam) * ex[idx]
