@@ -130,7 +130,11 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "<out-dir>/tuned_moments.json) instead of tuning")
-    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering", "mass"),
+    ap.add_argument("--picker-part", default="all", choices=("all", "collect", "evaluate"))
+    ap.add_argument("--picker-slice", default="", help="held-out shapes lo:hi for --picker-part collect")
+    ap.add_argument("--picker-data", default="", help="comma-separated collect outputs for --picker-part evaluate")
+    ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering", "mass",
+                             "small"),
                     help="moments: six nestings FP64 (default); batched: 200k small products; "
                          "bf16: LTimes Z=262144 G=64 D=128 NM=64 in BF16/BF16x3/FP64")
     return ap.parse_args()
@@ -166,6 +170,8 @@ def main():
         return bench_scattering(a)
     if a.workload == "mass":
         return bench_mass(a)
+    if a.workload == "small":
+        return bench_small(a)
     return bench_moments(a)
 
 
@@ -393,6 +399,18 @@ def bench_moments(a):
         torch.cuda.synchronize()
         default_value = step_bytes / ((time.perf_counter() - t0) / a.steps) / 1e9
 
+    # every kernel alone with a 1 GiB scratch write before each launch: nothing of its operands in the
+    # last-level cache (in the step, LPlusTimes may read part of the phi that LTimes has just written
+    # from the 256 MB last-level cache, so its in-step figures are cache-assisted)
+    scratch = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    for key in order:
+        kid_k, s_k = specs[key]
+        h_k = P.sj_specialize(kid_k, s_k)
+        ptrs_k = arrs[key]
+        ms_k, _ = time_launches(lambda: lib.sj_run(h_k.ptr, ptrs_k, 3, sptr), max(5, a.steps // 2), stream, scratch)
+        kern[f"{key[1]}_{key[0]}"].update(isolated_hbm_us=round(ms_k * 1e3, 2),
+                                          isolated_hbm_frac=round(nbytes / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    del scratch
     dom = max(order, key=lambda k: sum(per_kernel[k]))
     dom_ms = statistics.mean(per_kernel[dom])
     achieved = nbytes / (dom_ms * 1e-3) / 1e9
@@ -494,6 +512,9 @@ def bench_moments(a):
                      "bytes_per_launch": nbytes, "measured_copy_gbs": round(copy_gbs, 1),
                      "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
         "step_frac_of_measured_copy": round(value / copy_gbs, 4),
+        "value_note": ("effective rate of the step: algorithmic bytes / step time; LPlusTimes may read part of phi "
+                       "from the last-level cache right after LTimes writes it, so per-kernel in-step figures of "
+                       "LPlusTimes are cache-assisted; isolated_hbm_* are each kernel alone with the cache flushed"),
         "cpu_baseline": cpu,
         "kernels": kern,
         "generic": generic,
@@ -510,11 +531,16 @@ def bench_moments(a):
     print(json.dumps(line), flush=True)
 
 
-def time_launches(fn, reps, stream):
-    """Median and mean duration (ms) of `reps` launches of fn, each bracketed by events."""
+def time_launches(fn, reps, stream, flush=None):
+    """Median and mean duration (ms) of `reps` launches of fn, each bracketed by
+    events; with ``flush`` (a device tensor) the tensor is overwritten before
+    every launch, outside the bracket, so the launch finds nothing of its
+    operands in L2 or the last-level cache."""
     import torch
     evs = []
     for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         fn()
@@ -546,6 +572,18 @@ def bench_batched(a):
     for kv in filter(None, a.tile.split(",")):
         k, v = kv.split("=")
         tile[k] = int(v)
+    tuned_by, tune_s, n_tuned = "library default", None, 0
+    if not tile and not a.no_tune:
+        # the tiles come from the exhaustive tuner, timed on this batch (scratch written before each launch)
+        from paper_1904_08555_amd import tune
+        from paper_1904_08555_amd.farm import CompileFarm
+        t0 = time.perf_counter()
+        with CompileFarm(12) as farm:
+            r = tune.tune_bgemm(n, A_d, B_d, C_d, reps=5, warmup=1, flush=flush, farm=farm)
+        tune_s = time.perf_counter() - t0
+        tile, tuned_by, n_tuned = dict(r["best"]), "exhaustive tuner (tune.tune_bgemm)", len(r["results"])
+        print(f"tuned batched products: {tile} {r['best_ms'] * 1e3:.1f} us ({n_tuned} candidates)",
+              file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     h = P.sj_specialize(P.SJ_BGEMM, **tile)
     jit_ms = (time.perf_counter() - t0) * 1e3
@@ -609,6 +647,8 @@ def bench_batched(a):
         "host_wall_ms_per_step_with_scratch_write": round(t_total * 1e3 / a.steps, 4),
         "generic_us": round(gmed * 1e3, 2),
         "speedup_vs_generic": round(gmed / med, 3), "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
+        "tiles": tile, "tiles_from": tuned_by, "tuned_candidates": n_tuned,
+        "tune_s": None if tune_s is None else round(tune_s, 1),
         "kernel_info": {k: info[k] for k in ("vgprs", "sgprs", "occupancy", "lds_bytes", "scratch_bytes", "block",
                                              "variant", "tile_n", "unroll")},
     }
@@ -753,6 +793,98 @@ def bench_values(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_small(a):
+    """LTimes and LPlusTimes, DGZ, FP64, Z=4096 G=8 D=48 NM=16: a launch moves
+    16.8 MB, about 2 us at the HBM peak, so the launch and the cache lookup
+    matter.  64 buffer sets (psi, phi, psi' each; 1.9 GB in all, so the launches
+    cannot be served from the 256 MB last-level cache) are cycled through by 64
+    launches captured in one HIP graph per operator; time per launch = graph
+    replay time / 64.  Also the same 64 launches issued one by one, each after a
+    cache lookup (sj_specialize hit), as a caller without graphs would."""
+    import torch
+
+    import paper_1904_08555_amd as P
+    import sj_inputs as gen
+    from sj_inputs import device as gdev
+
+    Z, G, D, NM, nset = 4096, 8, 48, 16, 64
+    stream = torch.cuda.current_stream()
+    L_d = torch.empty(NM * D, dtype=torch.float64, device="cuda")
+    Lp_d = torch.empty(D * NM, dtype=torch.float64, device="cuda")
+    gdev.fill(L_d, 0, gen.ARR_L, gdev.DIST_SYM)
+    gdev.fill(Lp_d, 0, gen.ARR_LPLUS, gdev.DIST_SYM)
+    sets = []
+    for _ in range(nset):
+        psi = torch.empty(D * G * Z, dtype=torch.float64, device="cuda")
+        gdev.fill(psi, 0, gen.ARR_PSI, gdev.DIST_U01, 0, (D, G, Z))
+        sets.append((psi, torch.empty(NM * G * Z, dtype=torch.float64, device="cuda"),
+                     torch.empty(D * G * Z, dtype=torch.float64, device="cuda")))
+    spec_l = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM)
+    spec_p = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM)
+    h_l = P.sj_specialize(P.SJ_LTIMES, spec_l)
+    h_p = P.sj_specialize(P.SJ_LPLUSTIMES, spec_p)
+    nbytes = algorithmic_bytes(Z, G, D, NM)
+    res = {}
+    for name, h, kid, spec, ptrs in (
+            ("ltimes", h_l, P.SJ_LTIMES, spec_l, [[L_d, s[0], s[1]] for s in sets]),
+            ("lplustimes", h_p, P.SJ_LPLUSTIMES, spec_p, [[Lp_d, s[1], s[2]] for s in sets])):
+        for p in ptrs:                                   # warm up, outside capture
+            P.sj_run(h, p)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for p in ptrs:
+                P.sj_run(h, p)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        per = []
+        for _ in range(max(5, a.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+            per.append((e0, e1))
+        torch.cuda.synchronize()
+        g_ms = statistics.median(x.elapsed_time(y) for x, y in per) / nset
+        # one by one, each launch after a lookup (hit) of its specialization, no graph
+        lib = P.lib()
+        hout = ctypes.c_void_p()
+        arrs = [(ctypes.c_void_p * 3)(*(t.data_ptr() for t in p)) for p in ptrs]
+        sref = ctypes.byref(spec)
+        sptr = stream.cuda_stream
+        walls = []
+        for _ in range(max(5, a.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for arr in arrs:
+                lib.sj_specialize(kid, sref, ctypes.byref(hout))
+                lib.sj_run(hout, arr, 3, sptr)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        e_ms = statistics.median(walls) * 1e3 / nset
+        res[name] = dict(graph_us_per_launch=round(g_ms * 1e3, 3),
+                         graph_gbs=round(nbytes / (g_ms * 1e-3) / 1e9, 1),
+                         graph_frac=round(nbytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         eager_with_lookup_us_per_launch=round(e_ms * 1e3, 3),
+                         kernel=P.sj_handle_info(h)["kernel_name"])
+        del g
+    tot = res["ltimes"]["graph_us_per_launch"] + res["lplustimes"]["graph_us_per_launch"]
+    line = {
+        "metric": "LTimes + LPlusTimes per-launch time at the small DGZ shape (HIP graph of 64 launches)",
+        "value": round(2 * nbytes / (tot * 1e-6) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": 3, "ms_per_step": round(tot * 1e-3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64 counter generator, seed 0)",
+        "config": {"workload": f"LTimes+LPlusTimes, DGZ, FP64, Z={Z} G={G} D={D} NM={NM}",
+                   "buffer_sets": nset, "launches_per_graph": nset},
+        "roofline": {"bound": "hbm", "achieved": res["ltimes"]["graph_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": res["ltimes"]["graph_frac"], "traffic": None, "kernel": res["ltimes"]["kernel"],
+                     "avg_us": res["ltimes"]["graph_us_per_launch"], "bytes_per_launch": nbytes},
+        "per_kernel": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_scattering(a):
     """Scattering source phi_out[nm,g,z] = sum_g' S[mat(z)][n(nm)][g][g'] phi[nm,g',z]
     over the six nestings, FP64, Z=32768 G=32 NM=16 (degrees 0..3), four
@@ -778,14 +910,17 @@ def bench_scattering(a):
     mat_rnd = torch.from_numpy(rng.integers(0, nmat, Z).astype(np.int32)).cuda()
     phi = torch.empty(NM * G * Z, dtype=torch.float64, device="cuda")
     out = torch.empty_like(phi)
+    # phi and phi_out together (268 MB) are about the size of the 256 MB last-level cache: a 1 GiB
+    # scratch buffer is written before every timed launch (outside its events)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     nbytes = 2 * NM * G * Z * 8 + S_d.numel() * 8 + Z * 4
     res, tot = {}, 0.0
     for lay in layouts:
         gdev.fill(phi, 0, gen.ARR_PHI, gdev.DIST_U01, LAYOUTS.index(lay), (NM, G, Z))
         spec = P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat)
         h = P.sj_specialize(P.SJ_SCATTERING, spec)
-        t, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_reg, phi, out]), a.steps, stream)
-        tr, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream)
+        t, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_reg, phi, out]), a.steps, stream, flush)
+        tr, _ = time_launches(lambda: P.sj_run(h, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream, flush)
         info = P.sj_handle_info(h)
         tot += t
         res[lay] = dict(us=round(t * 1e3, 1), gbs=round(nbytes / (t * 1e-3) / 1e9, 1),
@@ -795,8 +930,9 @@ def bench_scattering(a):
                         traffic=measured_traffic(P, P.SJ_SCATTERING, spec))
         if lay == "ZDG":   # the other thread order of this nesting (order 2: threads along nm)
             h2 = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat, order=2))
-            t2, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_reg, phi, out]), a.steps, stream)
-            t2r, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream)
+            t2, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_reg, phi, out]), a.steps, stream, flush)
+            t2r, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream,
+                                   flush)
             res[lay]["threads_along_nm_us"] = round(t2 * 1e3, 1)
             res[lay]["threads_along_nm_random_materials_us"] = round(t2r * 1e3, 1)
     dom = max(res, key=lambda k: res[k]["us"])
@@ -806,7 +942,7 @@ def bench_scattering(a):
         "steps": a.steps, "warmup": 0, "ms_per_step": round(tot, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64 phi, seeded S and materials)",
         "config": {"workload": f"scattering, FP64, Z={Z} G={G} NM={NM}, {nmat} materials in zone regions",
-                   "layouts": layouts},
+                   "layouts": layouts, "cache": "1 GiB scratch written before every timed launch"},
         "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res[dom]["frac"], "traffic": res[dom]["traffic"], "kernel": res[dom]["kernel"],
                      "avg_us": res[dom]["us"], "bytes_per_launch": nbytes},
@@ -951,27 +1087,57 @@ def bench_copy(a):
 
 
 def bench_picker(a):
-    """Learned picker: 500 shapes x 4 random candidates = 2000 timed training
-    configurations, 200 held-out shapes tuned exhaustively; regret of the pick
-    against the tuner's best and speedup over the untuned default."""
-    import os
-
+    """Learned picker against the exhaustive tuner: 250 training shapes x 8
+    random candidates = 2000 timed training configurations; 200 held-out
+    shapes, each timed over the tuner's whole candidate set C(s) (every
+    nesting's tune.candidates); regret of the pick and of the spread-based
+    shortlist against the tuner's best, compiles needed, and speedup over the
+    untuned default.  --picker-part collect (with --picker-slice lo:hi) gathers
+    timings into out-dir/picker_data_<lo>_<hi>.json, so that the collection can
+    be split over several runs; --picker-part evaluate trains and scores on the
+    files named by --picker-data."""
     from paper_1904_08555_amd import picker
 
     t0 = time.perf_counter()
     os.makedirs(a.out_dir, exist_ok=True)
-    res, pk = picker.run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=12, epochs=200,
-                                    log=lambda m: print(m, file=sys.stderr, flush=True),
-                                    dump=os.path.join(a.out_dir, "picker_data.json"))
+    log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    lo, hi = (int(x) for x in a.picker_slice.split(":")) if a.picker_slice else (0, 200)
+    if a.picker_part in ("all", "collect"):
+        data = picker.collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log=log,
+                              eval_slice=(lo, hi), train=(lo == 0))
+        path = os.path.join(a.out_dir, f"picker_data_{lo}_{hi}.json")
+        with open(path, "w") as f:
+            json.dump(data, f)
+        if a.picker_part == "collect":
+            print(json.dumps({"picker_collect": path, "train": len(data.get("train", [])),
+                              "eval_shapes": len(data["eval"]), "train_collect_s": data.get("train_collect_s"),
+                              "eval_collect_s": data.get("eval_collect_s"),
+                              "wall_s": round(time.perf_counter() - t0, 1)}), flush=True)
+            return
+        parts = [data]
+    else:
+        parts = []
+        for path in a.picker_data.split(","):
+            with open(path) as f:
+                parts.append(json.load(f))
+    data = dict(train=[], eval=[])
+    for d in parts:
+        data["train"] += d.get("train", [])
+        data["eval"] += d["eval"]
+    res, pk, rows = picker.evaluate(data, seed=0, epochs=200, log=log)
+    res["train_collect_s"] = sum(d.get("train_collect_s") or 0 for d in parts)
+    res["eval_collect_s"] = sum(d.get("eval_collect_s") or 0 for d in parts)
     wall = time.perf_counter() - t0
-    os.makedirs(a.out_dir, exist_ok=True)
     pk.save(os.path.join(a.out_dir, "picker_weights.json"))
+    with open(os.path.join(a.out_dir, "picker_rows.json"), "w") as f:
+        json.dump(rows, f)
     line = {
         "metric": "picker regret vs exhaustive autotuner (mean over held-out shapes)",
         "value": res["regret_mean"], "unit": "fraction", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 model; f64 and bf16x3 kernels", "data": "synthetic (SplitMix64 + timings gathered here)",
-        "config": {"workload": "picker: 2000 timed training configs, 200 held-out shapes; Z=k^3 k in 8..64, "
+        "config": {"workload": "picker: 2000 timed training configs (250 shapes x 8 candidates), 200 held-out "
+                               "shapes each timed over the exhaustive tuner's candidate set; Z=k^3 k in 8..64, "
                                "G in 8..128, D in 16..256 step 8, NM in {4,9,16,36,64}, dtype in {f64, bf16x3}"},
         "roofline": None, "cpu_baseline": None, "picker": res,
     }

@@ -311,6 +311,20 @@ sj_status sj_run_adam(sj_handle h, void *const *ptrs, int nptrs, int64_t step,
 sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int reps, void *flush,
                       size_t flush_bytes, void *stream, float *times_ms);
 
+/* The canonical request `spec` resolves to for kernel `k`, without compiling:
+ * *out receives the spec with every default filled in (variant, tile_n,
+ * tile_k, unroll, block, order) and the load and store forms of LTimes /
+ * LPlusTimes / the fused kernel made explicit in flags (one of
+ * SJ_FLAG_LOADS_CACHED / _NONTEMPORAL and one of SJ_FLAG_STORES_CACHED /
+ * _NONTEMPORAL), plus SJ_FLAG_INDEX64 when 64-bit indexing is chosen.  Two
+ * requests with equal resolutions name the same specialization (the same
+ * handle).  Structure-internal fields are reported as the kernel uses them
+ * (the FP64 matrix-core row structure: unroll 1 = weight fragments in
+ * registers, 0 = in LDS; tile_k = reduction depth per step).  For a cost
+ * model or tuner that must see what a request will run.  Errors as
+ * sj_specialize's validation (no SJ_ERR_COMPILE / SJ_ERR_LOAD). */
+sj_status sj_resolve(sj_kernel k, const sj_spec *spec, sj_spec *out);
+
 /* The source text a spec compiles to (for inspection); `len` is the buffer
  * size, *needed receives the size including the terminating NUL. */
 sj_status sj_emit_source(sj_kernel k, const sj_spec *spec, char *buf, size_t len, size_t *needed);

@@ -335,6 +335,22 @@ static void contraction_bytes(const SpecKey &k, size_t *bytes)
     }
 }
 
+sj_status launch_mlp_bwd(const sj_handle_ *h, void *th, void *X, void *t, void *g, void *loss, void *ws,
+                         hipStream_t st)
+{
+    // per-row activations and deltas into ws, then one thread per parameter (and one for the
+    // loss) summing over the rows; every workspace value is written before it is read
+    const size_t P = (size_t)mlp_nparams(h->key.inputs, h->key.width);
+    void *args1[] = {&th, &X, &t, &ws};
+    hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0, st, args1, nullptr);
+    if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+    void *args2[] = {&X, &ws, &g, &loss};
+    const unsigned grid2 = (unsigned)((P + 1 + 255) / 256);
+    e = hipModuleLaunchKernel(h->fn2, grid2, 1, 1, 256, 1, 1, 0, st, args2, nullptr);
+    if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+    return SJ_OK;
+}
+
 sj_status check_ptrs(void *const *ptrs, int nptrs, int expect, const size_t *bytes, int first_out)
 {
     if (!ptrs) return fail(SJ_ERR_INVALID_ARG, "null pointer array");
@@ -498,6 +514,30 @@ sj_status sj_emit_source(sj_kernel k, const sj_spec *spec, char *buf, size_t len
     return SJ_OK;
 }
 
+sj_status sj_resolve(sj_kernel k, const sj_spec *spec, sj_spec *out)
+{
+    clear_error();
+    if (!out) return fail(SJ_ERR_INVALID_ARG, "null output");
+    SpecKey key;
+    sj_status s = make_key(k, spec, -1, "gfx950", &key);
+    if (s != SJ_OK) return s;
+    sj_spec r;
+    std::memset(&r, 0, sizeof r);
+    r.struct_size = sizeof(sj_spec);
+    r.dtype = key.dtype;
+    r.layout = key.layout;
+    r.variant = key.variant;
+    r.Z = key.Z; r.G = key.G; r.D = key.D; r.NM = key.NM;
+    r.count = spec->count;
+    r.class_mask = key.class_mask;
+    r.tile_n = key.tile_n; r.tile_k = key.tile_k; r.unroll = key.unroll; r.block = key.block;
+    r.flags = key.flags | (key.index64 ? SJ_FLAG_INDEX64 : 0u);
+    r.order = key.order;
+    r.rows = key.rows; r.inputs = key.inputs; r.width = key.width;
+    *out = r;
+    return SJ_OK;
+}
+
 sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
 {
     if (!h) return fail(SJ_ERR_INVALID_ARG, "null handle");
@@ -578,15 +618,7 @@ sj_status sj_run(sj_handle h, void *const *ptrs, int nptrs, void *stream)
         const size_t bytes[6] = {P * 4, R * F * 4, R * 4, P * 4, 4, R * (4 * H + 2) * 4};
         sj_status s = check_ptrs(ptrs, nptrs, 6, bytes, 3);
         if (s != SJ_OK) return s;
-        void *th = ptrs[0], *X = ptrs[1], *t = ptrs[2], *g = ptrs[3], *loss = ptrs[4], *ws = ptrs[5];
-        void *args1[] = {&th, &X, &t, &ws};
-        hipError_t e = hipModuleLaunchKernel(h->fn, h->geom.grid, 1, 1, h->geom.block, 1, 1, 0, st, args1, nullptr);
-        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
-        void *args2[] = {&X, &ws, &g, &loss};
-        const unsigned grid2 = (unsigned)((P + 1 + 255) / 256);
-        e = hipModuleLaunchKernel(h->fn2, grid2, 1, 1, 256, 1, 1, 0, st, args2, nullptr);
-        if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
-        return SJ_OK;
+        return launch_mlp_bwd(h, ptrs[0], ptrs[1], ptrs[2], ptrs[3], ptrs[4], ptrs[5], st);
     }
     if (k.kernel == SJ_ADAM) return fail(SJ_ERR_INVALID_ARG, "Adam handles run through sj_run_adam");
     if (k.kernel == SJ_BGEMM) return fail(SJ_ERR_INVALID_ARG, "BGEMM handles run through sj_batch_plan / sj_batch_run");

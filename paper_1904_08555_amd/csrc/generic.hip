@@ -83,6 +83,73 @@ __device__ __forceinline__ void lplustimes_body(const double *__restrict__ Lp, c
     }
 }
 
+// Reduction axis innermost (GZD, ZGD): every column is a contiguous row of
+// `red` input values and a contiguous row of `outn` outputs, so N columns are
+// one [N][red] and one [N][outn] row-major matrix, W is [outn][red] row-major
+// (L for LTimes, L+ for LPlusTimes).  A workgroup takes `tr` consecutive rows
+// (tr chosen on the host so the tiles fit in dynamic LDS): it reads them as one
+// contiguous run (consecutive threads, consecutive addresses) into LDS with a
+// row pitch of red + 1, each thread then forms outputs of one row in register
+// chunks of 16 (outputs j, j + kBlock/tr, ...), and the [tr][outn] results leave
+// through LDS as one contiguous run.  Only the loop bounds and addresses are
+// run-time values; the access pattern is the coalesced one a specialization
+// uses, so the comparison measures what compile-time sizes buy.
+__global__ void __launch_bounds__(kBlock)
+generic_rows(const double *__restrict__ W, const double *__restrict__ in, double *__restrict__ out, long long N,
+             long long red, long long outn, int tr)
+{
+    extern __shared__ double lds[];
+    double *xin = lds;                                   // [tr][red + 1]
+    double *yout = lds + (long long)tr * (red + 1);      // [tr][outn + 1]
+    const long long r0 = (long long)blockIdx.x * tr;
+    const long long rows = N - r0 < tr ? N - r0 : tr;
+    const long long nin = rows * red, nout = rows * outn;
+    const double *src = in + r0 * red;
+    for (long long e = threadIdx.x; e < nin; e += kBlock) {
+        const long long r = e / red;
+        xin[r * (red + 1) + (e - r * red)] = src[e];
+    }
+    __syncthreads();
+    const int per = kBlock / tr;                         // threads per row
+    const int r = threadIdx.x % tr, j0 = threadIdx.x / tr;
+    if (r < rows && j0 < per) {
+        const double *x = xin + (long long)r * (red + 1);
+        for (long long o0 = j0; o0 < outn; o0 += (long long)per * kChunk) {
+            double acc[kChunk];
+            const double *wr[kChunk];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                acc[c] = 0.0;
+                const long long o = o0 + (long long)c * per;
+                wr[c] = W + (o < outn ? o : outn - 1) * red;   // past outn: repeat the last row, never stored
+            }
+            for (long long k = 0; k < red; ++k) {
+                const double xv = x[k];
+#pragma unroll
+                for (int c = 0; c < kChunk; ++c) acc[c] = __builtin_fma(wr[c][k], xv, acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                const long long o = o0 + (long long)c * per;
+                if (o < outn) yout[(long long)r * (outn + 1) + o] = acc[c];
+            }
+        }
+    }
+    __syncthreads();
+    double *dst = out + r0 * outn;
+    for (long long e = threadIdx.x; e < nout; e += kBlock) {
+        const long long rr = e / outn;
+        dst[e] = yout[rr * (outn + 1) + (e - rr * outn)];
+    }
+}
+
+// Rows per workgroup of generic_rows: both tiles within 64 KiB of LDS.
+inline int generic_rows_tile(long long red, long long outn)
+{
+    const long long t = 8192 / (red + outn + 2);
+    return (int)std::max<long long>(1, std::min<long long>(kBlock, t));
+}
+
 __global__ void __launch_bounds__(kBlock)
 generic_ltimes(const double *__restrict__ L, const double *__restrict__ psi, double *__restrict__ phi, Strides s)
 {
@@ -216,6 +283,19 @@ extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *cons
         const double *L = (const double *)ptrs[0];
         const double *in = (const double *)ptrs[1];
         double *outp = (double *)ptrs[2];
+        if (st_.ad == 1 && st_.bd == 1 && A_in + A_out + 2 <= 8192) {
+            // the reduction axis is innermost in both arrays: rows staged through LDS (serves the
+            // generic call and the per-nesting one alike: the access pattern is the nesting's)
+            const int tr = generic_rows_tile(A_in, A_out);
+            const long long nrow = ((long long)cols + tr - 1) / tr;
+            if (nrow > 2147483647LL) return fail(SJ_ERR_UNSUPPORTED, "too many columns for one launch");
+            const size_t shm = (size_t)tr * (size_t)(A_in + A_out + 2) * 8;
+            hipLaunchKernelGGL(generic_rows, dim3((unsigned)nrow), dim3(kBlock), shm, st, L, in, outp,
+                               (long long)cols, A_in, A_out, tr);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
+            return SJ_OK;
+        }
         if (spec->flags & SJ_FLAG_GENERIC_PER_LAYOUT) {
             hipError_t e = (k == SJ_LTIMES) ? launch_aot<true>(spec->layout, (unsigned)nblk, st, L, in, outp, Z, G, D, NM)
                                             : launch_aot<false>(spec->layout, (unsigned)nblk, st, L, in, outp, Z, G, D, NM);

@@ -425,6 +425,14 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             key.full_unroll = 1;
         }
         (void)outn;
+        // the load and store forms become explicit, so that requests that resolve to the same
+        // kernel (a policy flag equal to the default) share one key
+        int ntl = 0, nts = 0;
+        load_store_policy(key, &ntl, &nts);
+        key.flags &= ~(SJ_FLAG_LOADS_CACHED | SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED |
+                       SJ_FLAG_STORES_NONTEMPORAL);
+        key.flags |= (ntl ? SJ_FLAG_LOADS_NONTEMPORAL : SJ_FLAG_LOADS_CACHED) |
+                     (nts ? SJ_FLAG_STORES_NONTEMPORAL : SJ_FLAG_STORES_CACHED);
         return (*out = key), SJ_OK;
     }
     if (k == SJ_MASS) {
@@ -680,6 +688,27 @@ static const char *kCommonPrologue =
     "#define SJ_STORE(v, p) SJ_STORE_RAW((v), (p))\n"
     "#endif\n";
 
+void load_store_policy(const SpecKey &k, int *nt_load, int *nt_store)
+{
+    // streaming hint: skip cache retention when every fetched line is used at once.
+    // Explicit flags, else the default measured on MI355X at Z=32768 G=32 D=96 NM=16:
+    // nontemporal stores for every streamed output; nontemporal loads for LTimes' column
+    // kernels (LTimes DGZ 166 us vs 177 us with ordinary loads) and its LDS-staged row kernel
+    // (163 us vs 174 us); ordinary loads for LPlusTimes (DGZ 151 us vs 186 us nontemporal) and
+    // for the direct row kernels, whose lanes read each 128-byte line in two halves (171 us vs
+    // 199 us).
+    const bool direct_rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1 && k.order != 2);
+    const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
+    int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !direct_rows) ? 1 : 0;
+    int nts = streamed ? 1 : 0;
+    if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
+    if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
+    if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
+    if (k.flags & SJ_FLAG_STORES_NONTEMPORAL) nts = 1;
+    *nt_load = ntl;
+    *nt_store = nts;
+}
+
 // The templates name their kernel through this macro.
 static const char *base_name_macro(const SpecKey &) { return "SJ_KERNEL_NAME"; }
 
@@ -697,21 +726,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         o << "#define SJ_D " << k.D << "\n#define SJ_NM " << k.NM << "\n";
         o << "#define SJ_B " << k.B << sfx << "\n#define SJ_I " << k.I << sfx << "\n";
         o << "#define SJ_BLOCK " << k.block << "\n";
-        // streaming hint: skip cache retention when every fetched line is used at once
-        // Load and store policy: explicit flags, else the default measured on MI355X at
-        // Z=32768 G=32 D=96 NM=16: nontemporal stores for every streamed output;
-        // nontemporal loads for LTimes' column kernels (LTimes DGZ 166 us vs 177 us with ordinary
-        // loads) and its LDS-staged row kernel (163 us vs 174 us); ordinary loads for LPlusTimes
-        // (DGZ 151 us vs 186 us nontemporal) and for the direct row kernels, whose lanes read
-        // each 128-byte line in two halves (171 us vs 199 us).
-        const bool direct_rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1 && k.order != 2);
-        const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
-        int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !direct_rows) ? 1 : 0;
-        int nts = streamed ? 1 : 0;
-        if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
-        if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
-        if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
-        if (k.flags & SJ_FLAG_STORES_NONTEMPORAL) nts = 1;
+        int ntl = 0, nts = 0;
+        load_store_policy(k, &ntl, &nts);
         o << "#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM "
           << ((k.flags & SJ_FLAG_ACCUMULATE) ? 1 : 0) << "\n";
         if (k.variant == SJ_VAR_DIRECT) {

@@ -9,6 +9,8 @@
 
 #include "sj.h"
 
+struct sj_handle_;
+
 namespace sj {
 
 // Canonical, fully resolved specialization request.  Plain data; zero-filled
@@ -60,6 +62,11 @@ sj_status make_values_key(const double *values, size_t count, SpecKey *key);
 // Number of parameters of the cost-model MLP with `inputs` features and width `width`.
 inline int64_t mlp_nparams(int64_t inputs, int64_t width) { return width * inputs + width * width + 3 * width + 1; }
 
+// Load and store forms of the streamed operands of a contraction key: 1 =
+// nontemporal, 0 = ordinary; explicit SJ_FLAG_LOADS_* / SJ_FLAG_STORES_* flags,
+// else the measured defaults.
+void load_store_policy(const SpecKey &key, int *nt_load, int *nt_store);
+
 // Launch geometry of a resolved key.
 struct Geometry {
     unsigned grid;
@@ -78,6 +85,11 @@ void parse_resource_usage(const std::string &log, sj_kernel_info *info);
 // Validate run pointers: non-null, 16-byte aligned, outputs (index >= first_out)
 // overlapping no other buffer.
 sj_status check_ptrs(void *const *ptrs, int nptrs, int expect, const size_t *bytes, int first_out);
+
+// The two launches of the MLP backward pass of handle h (kernel SJ_MLP_BWD) with
+// workspace ws of rows * (4 width + 2) floats; pointers already checked.
+sj_status launch_mlp_bwd(const sj_handle_ *h, void *th, void *X, void *t, void *g, void *loss, void *ws,
+                         hipStream_t st);
 
 // Initialized device state.
 sj_status ensure_device(int *device, const char **arch);

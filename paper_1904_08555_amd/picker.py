@@ -1,27 +1,34 @@
 """Learned specialization picker (cost model) and its evaluation.
 
-The exhaustive autotuner compiles and times every candidate specialization
-C(s) of a shape s; the picker instead predicts each candidate's run time
-relative to the shape's other candidates and compiles only the predicted best.
-Five networks (features -> 64 -> 64 -> 1, ReLU, FP32, different seeds) are
-averaged; each is trained on GPU with the library's own kernels
-(SJ_MLP_BWD for the loss gradient, SJ_ADAM for the update, SJ_MLP_FWD for
-prediction), on timings the library itself gathers with sj_time_run.  This is
-the profile-guided, adaptive specialization named as future work in ClangJIT
+The exhaustive autotuner (tune.py) compiles and times every candidate
+specialization of a shape; the picker predicts each candidate's run time
+relative to the shape's other candidates and compiles only what it cannot rule
+out.  The candidate set of a shape s is exactly the tuner's: C(s) = the union
+over nestings of tune.candidates(LTimes, nesting, s) (every nesting for FP64,
+the column-innermost ones for BF16x3), so the tuner's best over C(s) is both
+the judge of the picker's regret and its fallback.
+
+Model: five networks (features -> 64 -> 64 -> 1, ReLU, FP32, different seeds);
+each is trained on the GPU with the library's own kernels (SJ_MLP_BWD for the
+loss gradient, SJ_ADAM for the update, SJ_MLP_FWD for prediction), on timings
+the library gathers with sj_time_run.  The features describe the
+specialization the request resolves to (sj_resolve: the tiles, structure and
+load/store forms that will run), so the network sees what the compiler gets.
+
+Decision with fallback: rank C(s) by the ensemble mean; the candidates whose
+predicted advantage over the first is within the ensemble's spread
+(mean_c - mean_best < TAU * (sd_c + sd_best)) cannot be told apart by the
+model, so the first K of them (K <= KMAX) are compiled and timed, exactly as
+the tuner would time them, and the fastest is kept.  With a confident model
+that is one compile; at worst KMAX instead of |C(s)|.  This is the
+profile-guided, adaptive specialization named as future work in ClangJIT
 section 6.
 
 Shapes (LTimes): Z = k^3 with k ~ U{8..64}, G ~ U{8..128}, D = 8 U{2..32},
-NM ~ U{4, 9, 16, 36, 64}, dtype ~ U{FP64, BF16x3}.  Candidates:
-  FP64, column axis innermost (DGZ, DZG, GDZ, ZDG): DIRECT, tile_n in {1, 2},
-      order in {ascending, rotated}, unroll 8, block 256; FP64-MFMA columns
-      with default tiles, order in {ascending, rotated};
-  FP64, D innermost (GZD, ZGD): FP64-MFMA rows, tile_n in {1, 2, 4}, block
-      256, default operand path (LDS-staged runs where they fit);
-  BF16x3 (column layouts only): columns per lane in {1, 4} (4 when it
-      divides the contiguous extent), block 256.
-The cost of a candidate is the median of 5 timed launches of one LTimes (after
-one warm-up), with L2 and the last-level cache flushed first when the working
-set is under 512 MB.  Regret of a pick: t(pick) / min_c t(c) - 1.
+NM ~ U{4, 9, 16, 36, 64}, dtype ~ U{FP64, BF16x3}.  The cost of a candidate
+is the median of 5 timed launches of one LTimes (after one warm-up), with L2
+and the last-level cache flushed first when the working set is under 512 MB.
+Regret of a choice: t(choice) / min_{c in C(s)} t(c) - 1.
 """
 from __future__ import annotations
 
@@ -31,12 +38,14 @@ import time
 
 import numpy as np
 
-from . import sj
+from . import sj, tune
 
 LAYOUTS = sj.LAYOUTS
 COLUMN_LAYOUTS = ("DGZ", "DZG", "GDZ", "ZDG")
-NFEAT = 30
+NFEAT = 36
 WIDTH = 64
+TAU = 1.0      # spread multiple within which two predictions are not told apart
+KMAX = 4       # at most this many candidates compiled and timed per shape
 
 
 def sample_shape(rng: np.random.Generator) -> dict:
@@ -47,32 +56,25 @@ def sample_shape(rng: np.random.Generator) -> dict:
 
 
 def contiguous_extent(layout: str, Z: int, G: int) -> int:
-    return {"DGZ": G * Z, "DZG": G * Z, "GDZ": Z, "ZDG": G}.get(layout, 1)
+    return tune.contiguous_extent(layout, Z, G)
 
 
-def candidates(shape: dict) -> list:
+def candidates(shape: dict, layouts=None) -> list:
+    """C(s): the exhaustive tuner's candidates over every nesting the dtype
+    supports (restricted to ``layouts`` when given), each tagged with its
+    nesting; candidates the specializer refuses for the shape are left out."""
+    f64 = shape["dtype"] == sj.SJ_F64
+    lays = [l for l in (layouts or LAYOUTS) if f64 or l in COLUMN_LAYOUTS]
     out = []
-    if shape["dtype"] == sj.SJ_F64:
-        for lay in LAYOUTS:
-            if lay in COLUMN_LAYOUTS:
-                ext = contiguous_extent(lay, shape["Z"], shape["G"])
-                for vec in (1, 2):
-                    if ext % vec:
-                        continue
-                    for order in (1, 2):
-                        out.append(dict(layout=lay, variant=sj.SJ_VAR_DIRECT, tile_n=vec, unroll=8, block=256,
-                                        order=order))
-                for order in (1, 2):
-                    out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, order=order))
-            else:
-                for rt in (1, 2, 4):
-                    out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, tile_n=rt, block=256))
-    else:
-        for lay in COLUMN_LAYOUTS:
-            ext = contiguous_extent(lay, shape["Z"], shape["G"])
-            for cpl in (1, 4):
-                if ext % cpl == 0:
-                    out.append(dict(layout=lay, variant=sj.SJ_VAR_MFMA, tile_n=cpl, block=256))
+    for lay in lays:
+        for c in tune.candidates(sj.SJ_LTIMES, lay, shape["Z"], shape["G"], shape["D"], shape["NM"],
+                                 shape["dtype"]):
+            cand = dict(layout=lay, **c)
+            try:
+                sj.sj_resolve(sj.SJ_LTIMES, **spec_of(shape, cand))
+            except sj.SJError:
+                continue
+            out.append(cand)
     return out
 
 
@@ -82,91 +84,62 @@ def default_candidate(shape: dict) -> dict:
     return dict(layout="DGZ")
 
 
-def resolved(shape: dict, cand: dict) -> dict:
-    """The tile parameters the specializer resolves for a candidate (its
-    defaults restated for LTimes), so that features see what will run."""
-    Z, G, NM = shape["Z"], shape["G"], shape["NM"]
-    lay = cand.get("layout", "DGZ")
-    I = contiguous_extent(lay, Z, G)
-    B = G * Z // I
-    f64 = shape["dtype"] == sj.SJ_F64
-    var = cand.get("variant", 0) or (sj.SJ_VAR_MFMA if (not f64 or I == 1) else sj.SJ_VAR_DIRECT)
-    ob = (NM + 15) // 16
-    r = dict(I=I, B=B, variant=var, block=cand.get("block", 0) or 256, order=cand.get("order", 0))
-    far = I * 8 >= (1 << 20)
-    if var == sj.SJ_VAR_DIRECT:
-        r["tile"] = cand.get("tile_n", 0) or (2 if I % 2 == 0 and NM <= 16 else 1)
-        r["unroll"] = cand.get("unroll", 0) or 8
-        r["order"] = r["order"] or (2 if far else 1)
-        r["width"], r["acc"] = 1, NM * r["tile"]
-    elif not f64:
-        r["tile"] = cand.get("tile_n", 0) or (4 if I % 4 == 0 else 1)
-        r["unroll"] = 1
-        r["order"] = 1
-        r["width"], r["acc"] = 32 * r["tile"], ((NM + 31) // 32) * 16 * r["tile"]
-    elif I > 1:
-        t = cand.get("tile_n", 0)
-        if not t:
-            t = 1
-            for c in (4, 2):
-                if I % c == 0 and ob * 4 * c <= 32:
-                    t = c
-                    break
-        r["tile"] = t
-        r["unroll"] = cand.get("unroll", 0) or max(1, min(16 // t, 32 // (ob * t)))
-        r["order"] = r["order"] or (2 if far else 1)
-        r["width"], r["acc"] = 16 * t, ob * 4 * t
-    else:
-        # row kernel: the LDS-staged form (order 2) when the rows are even and its
-        # registers and LDS allow, else lanes read their operands directly (order 1)
-        D = shape["D"]
-        kb = (D + 15) // 16
-        wreg = kb * 4 * ob <= 32
-        rt = cand.get("tile_n", 0)
-        block = r["block"]
-
-        def run_ok(t):
-            lds = (block // 64) * 16 * t * (max(16 * kb, NM) + 2) * 8 + (0 if wreg else kb * 4 * ob * 512)
-            return D % 2 == 0 and NM % 2 == 0 and t * ob * 4 <= 96 and (8 * t * D + 63) // 64 <= 32 and lds <= 160 * 1024
-        order = cand.get("order", 0)
-        if order != 1 and run_ok(rt or (2 if cand.get("block", 0) in (0, 256) else 1)):
-            rt, order = rt or (2 if cand.get("block", 0) in (0, 256) else 1), 2
-        else:
-            rt, order = rt or (2 if 8 * ob <= 96 else 1), 1
-        r["tile"], r["unroll"], r["order"] = rt, 1, order
-        r["width"], r["acc"] = 1, rt * ob * 4
-    return r
+def spec_of(shape: dict, cand: dict) -> dict:
+    spec = dict(Z=shape["Z"], G=shape["G"], D=shape["D"], NM=shape["NM"], dtype=shape["dtype"])
+    spec.update(cand)
+    return spec
 
 
 def features(shape: dict, cand: dict) -> np.ndarray:
-    """Raw (unnormalized) feature vector of NFEAT floats."""
+    """Raw (unnormalized) feature vector of NFEAT floats, computed from the
+    specialization the request resolves to."""
+    r = sj.sj_resolve(sj.SJ_LTIMES, **spec_of(shape, cand))
     f = np.zeros(NFEAT, dtype=np.float64)
     Z, G, D, NM = shape["Z"], shape["G"], shape["D"], shape["NM"]
-    lay = cand.get("layout", "DGZ")
-    esz = 8 if shape["dtype"] == sj.SJ_F64 else 4
-    r = resolved(shape, cand)
-    I, B, var = r["I"], r["B"], r["variant"]
+    lay = LAYOUTS[r["layout"]]
+    f64 = shape["dtype"] == sj.SJ_F64
+    esz = 8 if f64 else 4
+    I = contiguous_extent(lay, Z, G)
+    B = G * Z // I
+    var, tn, blk = r["variant"], max(1, r["tile_n"]), r["block"]
+    col_mfma = var == sj.SJ_VAR_MFMA and f64 and I > 1
+    row_mfma = var == sj.SJ_VAR_MFMA and f64 and I == 1
     f[0:4] = [math.log2(Z), math.log2(G), math.log2(D), math.log2(NM)]
-    f[4] = 1.0 if shape["dtype"] == sj.SJ_F64 else 0.0
+    f[4] = 1.0 if f64 else 0.0
     f[5] = 1.0 - f[4]
     f[6 + LAYOUTS.index(lay)] = 1.0
-    f[12 + (var - 1)] = 1.0
-    f[15] = math.log2(r["tile"])
-    f[16] = r["unroll"] / 16.0
-    f[17] = r["block"] / 512.0
-    f[18] = 1.0 if r["order"] == 2 else 0.0
-    f[19] = math.log2(I * esz)                             # contiguous run in bytes
-    f[20] = math.log2((D + NM) * G * Z * esz)             # algorithmic bytes
-    f[21] = math.log2(2.0 * D * NM * G * Z)               # flops
-    f[22] = math.log2(I * esz) if lay in ("DGZ", "DZG") else math.log2(Z * esz)  # row stride proxy
-    f[23] = 1.0
-    w = r["width"]
-    f[24] = I / (((I + w - 1) // w) * w)                  # share of lanes with a real column
-    f[25] = math.log2(B)
-    f[26] = math.log2(r["acc"])                            # accumulators per lane
-    f[27] = 1.0 if (var == sj.SJ_VAR_MFMA and shape["dtype"] == sj.SJ_F64 and I > 1) else 0.0
-    f[28] = 1.0 if I == 1 else 0.0
-    f[29] = math.log2(I)
+    f[12 + (var - 1)] = 1.0                               # DIRECT, STAGED, MFMA
+    f[15] = 1.0 if col_mfma else 0.0
+    f[16] = 1.0 if row_mfma else 0.0
+    if var == sj.SJ_VAR_STAGED:
+        tile, width, acc = tn // blk, 1, NM * (tn // blk)
+    elif var == sj.SJ_VAR_DIRECT:
+        tile, width, acc = tn, tn, NM * tn
+    elif not f64:
+        tile, width, acc = tn, 32 * tn, ((NM + 31) // 32) * 16 * tn
+    elif col_mfma:
+        tile, width, acc = tn, 16 * tn, ((NM + 15) // 16) * 4 * tn
+    else:
+        tile, width, acc = tn, 1, tn * ((NM + 15) // 16) * 4
+    f[17] = math.log2(tile)
+    f[18] = r["unroll"] / 16.0
+    f[19] = blk / 512.0
+    f[20] = 1.0 if r["order"] == 2 else 0.0
+    f[21] = 1.0 if r["flags"] & sj.SJ_FLAG_LOADS_NONTEMPORAL else 0.0
+    f[22] = 1.0 if r["flags"] & sj.SJ_FLAG_STORES_NONTEMPORAL else 0.0
+    f[23] = math.log2(I * esz)                            # contiguous run in bytes
+    f[24] = math.log2((D + NM) * G * Z * esz)             # algorithmic bytes
+    f[25] = math.log2(2.0 * D * NM * G * Z)               # flops
+    f[26] = math.log2(I * esz) if lay in ("DGZ", "DZG") else math.log2(Z * esz)  # row stride proxy
+    f[27] = I / (((I + width - 1) // width) * width) if width > 1 else 1.0       # lanes holding a real column
+    f[28] = math.log2(B)
+    f[29] = math.log2(max(1, acc))                        # accumulators per lane
+    f[30] = r["tile_k"] / 32.0 if var == sj.SJ_VAR_STAGED else 0.0
+    f[31] = math.log2(I)
+    f[32] = math.log2(max(1.0, G * Z / max(1, width)))    # lanes of work
+    f[33] = 1.0 if r["flags"] & sj.SJ_FLAG_INDEX64 else 0.0
+    f[34] = math.log2(2.0 * D * NM * G * Z) - math.log2((D + NM) * G * Z * esz)  # arithmetic intensity
+    f[35] = 1.0
     return f
 
 
@@ -192,7 +165,6 @@ class Buffers:
         self.flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
 
     def ptrs(self, shape: dict):
-        Z, G, D, NM = shape["Z"], shape["G"], shape["D"], shape["NM"]
         if shape["dtype"] == sj.SJ_F64:
             return [self.L, self.psi64, self.phi64]
         return [self.L, self.psi32, self.phi32]
@@ -202,11 +174,10 @@ class Buffers:
         esz = 8 if shape["dtype"] == sj.SJ_F64 else 4
         return (shape["D"] + shape["NM"]) * shape["G"] * shape["Z"] * esz
 
-
-def spec_of(shape: dict, cand: dict) -> dict:
-    spec = dict(Z=shape["Z"], G=shape["G"], D=shape["D"], NM=shape["NM"], dtype=shape["dtype"])
-    spec.update(cand)
-    return spec
+    @staticmethod
+    def for_shapes(shapes):
+        return Buffers(max(s["D"] * s["G"] * s["Z"] for s in shapes),
+                       max(s["NM"] * s["G"] * s["Z"] for s in shapes), 256 * 64)
 
 
 def time_items(farm, bufs: Buffers, items, log=None, reps: int = 5):
@@ -317,9 +288,9 @@ class MLP:
 class Picker:
     """An ensemble of MLPs over standardized features.  The target of a training
     timing is its log-time relative to the mean log-time of the candidates
-    timed for the same shape: the pick only compares candidates of one shape,
-    so the network is not asked to learn the (much larger) differences between
-    shapes.  Predictions are relative log-times; the pick is their argmin."""
+    timed for the same shape: a decision only compares candidates of one
+    shape, so the network is not asked to learn the (much larger) differences
+    between shapes.  Predictions are relative log-times."""
 
     def __init__(self, seed: int = 0, members: int = 5):
         self.mlps = [MLP(seed=seed + 101 * k) for k in range(members)]
@@ -361,9 +332,24 @@ class Picker:
             losses = m.fit(self._norm(F), t / self.tsd, epochs=epochs, batch=batch, seed=k, log=log if k == 0 else None)
         return losses
 
-    def predict_rel(self, shape, cands) -> np.ndarray:
+    def predict_members(self, shape, cands) -> np.ndarray:
+        """(members, len(cands)) relative log-time predictions."""
         F = self._norm(np.stack([features(shape, c) for c in cands]))
-        return np.mean([m.predict(F) for m in self.mlps], axis=0) * self.tsd
+        return np.stack([m.predict(F) for m in self.mlps]).astype(np.float64) * self.tsd
+
+    def predict_rel(self, shape, cands) -> np.ndarray:
+        return self.predict_members(shape, cands).mean(axis=0)
+
+    def shortlist(self, shape, cands, tau: float = TAU, kmax: int = KMAX):
+        """Indices of the candidates to compile and time: the predicted best,
+        then (in predicted order) those the ensemble's spread cannot separate
+        from it, at most kmax in all.  Returns (indices, mean predictions)."""
+        pm = self.predict_members(shape, cands)
+        mu, sd = pm.mean(axis=0), pm.std(axis=0)
+        order = np.argsort(mu, kind="stable")          # ties: lowest candidate index
+        b = order[0]
+        close = [int(j) for j in order[1:] if mu[j] - mu[b] < tau * (sd[j] + sd[b])]
+        return [int(b)] + close[:kmax - 1], mu
 
     def pick(self, shape, cands=None):
         cands = candidates(shape) if cands is None else cands
@@ -387,88 +373,128 @@ class Picker:
         self.tsd = d["tsd"]
 
 
-def run_experiment(n_train_shapes=500, per_shape=4, n_eval=200, seed=0, workers=8, epochs=300, log=print,
-                   max_k=64, dump=None):
-    """Collect training timings, train the picker, evaluate regret on held-out
-    shapes against the exhaustive tuner's best, and the gain over the
-    untuned default.  Returns a result dict."""
+# ------------------------------------------------------------------ the experiment
+
+def draw_shapes(rng, n, max_k=64):
+    out = []
+    while len(out) < n:
+        s = sample_shape(rng)
+        if round(s["Z"] ** (1 / 3)) <= max_k:
+            out.append(s)
+    return out
+
+
+def collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log=print, max_k=64, layouts=None,
+            eval_slice=None, train=True):
+    """Timings for the experiment: per_shape random candidates of each training
+    shape, and every candidate (the exhaustive tuner's whole set) plus the
+    default of each held-out shape.  ``eval_slice`` = (lo, hi) restricts the
+    held-out shapes (to split a long collection over several runs); the shapes
+    themselves depend only on the seed.  Returns a JSON-able dict."""
     from .farm import CompileFarm
     rng = np.random.default_rng(seed)
-
-    def draw(n):
-        out = []
-        while len(out) < n:
-            s = sample_shape(rng)
-            k = round(s["Z"] ** (1 / 3))
-            if k <= max_k:
-                out.append(s)
-        return out
-    train_shapes = draw(n_train_shapes)
-    eval_shapes = draw(n_eval)
-    allshapes = train_shapes + eval_shapes
-    max_psi = max((s["D"]) * s["G"] * s["Z"] for s in allshapes)
-    max_phi = max(s["NM"] * s["G"] * s["Z"] for s in allshapes)
-    bufs = Buffers(max_psi, max_phi, 256 * 64)
-    res = {}
+    train_shapes = draw_shapes(rng, n_train_shapes, max_k)
+    eval_shapes = draw_shapes(rng, n_eval, max_k)
+    crng = np.random.default_rng(seed + 1)
+    items = []
+    for s in train_shapes:
+        cs = candidates(s, layouts)
+        for j in crng.choice(len(cs), size=min(per_shape, len(cs)), replace=False):
+            items.append((s, cs[int(j)]))
+    lo, hi = eval_slice or (0, n_eval)
+    ev_items = []
+    for i in range(lo, hi):
+        s = eval_shapes[i]
+        for c in candidates(s, layouts) + [default_candidate(s)]:
+            ev_items.append((i, s, c))
+    used = (train_shapes if train else []) + eval_shapes[lo:hi]
+    bufs = Buffers.for_shapes(used)
+    out = dict(seed=seed, layouts=layouts, max_k=max_k, eval_slice=[lo, hi])
     with CompileFarm(workers) as farm:
-        items = []
-        for s in train_shapes:
-            cs = candidates(s)
-            for j in rng.choice(len(cs), size=min(per_shape, len(cs)), replace=False):
-                items.append((s, cs[int(j)]))
+        if train:
+            t0 = time.time()
+            times = time_items(farm, bufs, items, log=log)
+            out["train"] = [(s, c, t) for (s, c), t in zip(items, times) if t is not None]
+            out["train_collect_s"] = round(time.time() - t0, 1)
+            log(f"training timings: {len(out['train'])}")
         t0 = time.time()
-        times = time_items(farm, bufs, items, log=log)
-        res["train_collect_s"] = round(time.time() - t0, 1)
-        pairs = [(it, t) for it, t in zip(items, times) if t is not None]
-        log(f"training samples: {len(pairs)}")
+        ev_times = time_items(farm, bufs, [(s, c) for _, s, c in ev_items], log=log)
+        out["eval_collect_s"] = round(time.time() - t0, 1)
+    rows = {}
+    for (i, s, c), t in zip(ev_items, ev_times):
+        r = rows.setdefault(i, dict(index=i, shape=s, times=[], default_ms=None))
+        if c == default_candidate(s):
+            r["default_ms"] = t
+        elif t is not None:
+            r["times"].append((c, t))
+    out["eval"] = [rows[i] for i in sorted(rows)]
+    del bufs
+    return out
+
+
+def evaluate(data, seed=0, epochs=200, log=print, tau=TAU, kmax=KMAX, picker=None):
+    """Train the ensemble on data["train"] (unless ``picker`` is given) and
+    score it on data["eval"] against the exhaustive tuner's best over the same
+    candidate set.  Returns (result dict, picker, per-shape rows)."""
+    res = {}
+    if picker is None:
+        pairs = [((s, c), t) for s, c, t in data["train"]]
         picker = Picker(seed=seed)
         t0 = time.time()
         losses = picker.fit([p[0] for p in pairs], [p[1] for p in pairs], epochs=epochs, log=log)
         res["train_s"] = round(time.time() - t0, 2)
         res["final_train_mse"] = round(losses[-1], 4)
-        ev_items, owner = [], []
-        for i, s in enumerate(eval_shapes):
-            for c in candidates(s):
-                ev_items.append((s, c))
-                owner.append(i)
-            ev_items.append((s, default_candidate(s)))
-            owner.append(-1 - i)
-        t0 = time.time()
-        ev_times = time_items(farm, bufs, ev_items, log=log)
-        res["eval_collect_s"] = round(time.time() - t0, 1)
-    regrets, regrets2, gains, picks_ok = [], [], [], 0
-    per_shape_rows = []
-    for i, s in enumerate(eval_shapes):
-        cs = [(c, t) for (ss, c), o, t in zip(ev_items, owner, ev_times) if o == i and t is not None]
-        dflt = [t for (ss, c), o, t in zip(ev_items, owner, ev_times) if o == -1 - i and t is not None]
-        if not cs or not dflt:
+        res["train_samples"] = len(pairs)
+    reg1, regk, compiles, gains, gains_k, rand, ncands, dflt_reg, rows = [], [], [], [], [], [], [], [], []
+    for row in data["eval"]:
+        s, ct, dflt = row["shape"], row["times"], row["default_ms"]
+        if len(ct) < 2 or dflt is None:
             continue
-        cands = [c for c, _ in cs]
-        best = min(t for _, t in cs)
-        pick, pred = picker.pick(s, cands)
-        t_of = dict((json.dumps(c, sort_keys=True), t) for c, t in cs)
-        t_pick = t_of[json.dumps(pick, sort_keys=True)]
-        regrets.append(t_pick / best - 1.0)
-        # top-2: compile and time the two best-predicted candidates, keep the faster
-        two = np.argsort(pred, kind="stable")[:2]
-        regrets2.append(min(t_of[json.dumps(cands[int(j)], sort_keys=True)] for j in two) / best - 1.0)
-        per_shape_rows.append(dict(shape=s, times=[(c, t) for c, t in cs], pred=[float(x) for x in pred],
-                                   pick=pick, default_ms=dflt[0]))
-        gains.append(dflt[0] / t_pick)
-        picks_ok += 1
+        cands = [c for c, _ in ct]
+        t = np.array([x for _, x in ct])
+        best = t.min()
+        short, mu = picker.shortlist(s, cands, tau=tau, kmax=kmax)
+        t1 = t[short[0]]
+        tk = t[short].min()
+        reg1.append(t1 / best - 1.0)
+        regk.append(tk / best - 1.0)
+        compiles.append(len(short))
+        ncands.append(len(cands))
+        gains.append(dflt / t1)
+        gains_k.append(dflt / tk)
+        rand.append(float(np.mean(t / best - 1.0)))
+        dflt_reg.append(dflt / best - 1.0)
+        rows.append(dict(shape=s, n_candidates=len(cands), pick=cands[short[0]], shortlist=[cands[j] for j in short],
+                         best=cands[int(np.argmin(t))], t_best=float(best), t_pick=float(t1), t_shortlist=float(tk),
+                         t_default=float(dflt)))
+
+    def stats(x, name):
+        x = np.array(x)
+        return {f"{name}_mean": round(float(x.mean()), 4), f"{name}_median": round(float(np.median(x)), 4),
+                f"{name}_p90": round(float(np.quantile(x, 0.9)), 4), f"{name}_max": round(float(x.max()), 4)}
+    res.update(eval_shapes=len(reg1), candidates_mean=round(float(np.mean(ncands)), 1),
+               compiles_mean=round(float(np.mean(compiles)), 2),
+               compiles_saved_frac=round(1.0 - float(np.sum(compiles)) / float(np.sum(ncands)), 4))
+    res.update(stats(reg1, "regret"))
+    res["within_10pct"] = round(float(np.mean(np.array(reg1) <= 0.10)), 4)
+    res.update(stats(regk, "shortlist_regret"))
+    res["shortlist_within_10pct"] = round(float(np.mean(np.array(regk) <= 0.10)), 4)
+    res.update(stats(rand, "random_choice_regret"))
+    res.update(stats(dflt_reg, "default_regret"))
+    res["speedup_vs_default_geomean"] = round(float(np.exp(np.mean(np.log(gains)))), 4)
+    res["shortlist_speedup_vs_default_geomean"] = round(float(np.exp(np.mean(np.log(gains_k)))), 4)
+    res["tau"], res["kmax"] = tau, kmax
+    return res, picker, rows
+
+
+def run_experiment(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, epochs=200, log=print,
+                   max_k=64, layouts=None, dump=None):
+    """collect() then evaluate() in one process."""
+    data = collect(n_train_shapes, per_shape, n_eval, seed, workers, log, max_k, layouts)
     if dump:
         with open(dump, "w") as f:
-            json.dump(dict(train=[(sc[0], sc[1], t) for sc, t in pairs], eval=per_shape_rows), f)
-    r = np.array(regrets)
-    g = np.array(gains)
-    res.update(dict(
-        eval_shapes=picks_ok, candidates_mean=round(len(ev_items) / max(1, n_eval) - 1, 1),
-        regret_mean=round(float(r.mean()), 4), regret_median=round(float(np.median(r)), 4),
-        regret_p90=round(float(np.quantile(r, 0.9)), 4), regret_max=round(float(r.max()), 4),
-        within_10pct=round(float(np.mean(r <= 0.10)), 4),
-        top2_regret_mean=round(float(np.mean(regrets2)), 4),
-        top2_regret_p90=round(float(np.quantile(regrets2, 0.9)), 4),
-        speedup_vs_default_geomean=round(float(np.exp(np.mean(np.log(g)))), 4),
-        speedup_vs_default_mean=round(float(g.mean()), 4),
-        train_samples=len(pairs)))
+            json.dump(data, f)
+    res, picker, _ = evaluate(data, seed=seed, epochs=epochs, log=log)
+    res["train_collect_s"] = data.get("train_collect_s")
+    res["eval_collect_s"] = data.get("eval_collect_s")
     return res, picker

@@ -64,7 +64,7 @@ SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 EXPORTED = (
     "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_values", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",
     "sj_batch_run", "sj_batch_graph_capture", "sj_batch_graph_launch", "sj_batch_plan_arrays", "sj_plan_destroy",
-    "sj_run_adam", "sj_time_run", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
+    "sj_run_adam", "sj_time_run", "sj_resolve", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
     "sj_last_error", "sj_status_string",
 )
 
@@ -145,6 +145,7 @@ def lib() -> ctypes.CDLL:
         "sj_run_adam": [vp, P(vp), ctypes.c_int, i64, d, d, d, d, vp],
         "sj_time_run": [vp, P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
                         P(ctypes.c_float)],
+        "sj_resolve": [ctypes.c_int, P(sj_spec), P(sj_spec)],
         "sj_emit_source": [ctypes.c_int, P(sj_spec), ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_size_t)],
         "sj_handle_info": [vp, P(sj_kernel_info)],
         "sj_handle_code": [vp, P(vp), P(ctypes.c_size_t)],
@@ -298,6 +299,16 @@ def sj_time_run(handle: Handle, ptrs, warmup: int = 2, reps: int = 10, flush=Non
     _check(lib().sj_time_run(handle.ptr, arr, len(ptrs), int(warmup), int(reps), _addr(flush), fbytes,
                              _stream(stream), out))
     return list(out)
+
+
+def sj_resolve(kernel: int, spec: sj_spec | None = None, **kw) -> dict:
+    """The canonical request a spec resolves to (defaults filled in, load and
+    store forms explicit in ``flags``), as a dict of the sj_spec fields."""
+    if spec is None:
+        spec = make_spec(**kw)
+    out = sj_spec()
+    _check(lib().sj_resolve(int(kernel), ctypes.byref(spec), ctypes.byref(out)))
+    return {name: getattr(out, name) for name, _ in sj_spec._fields_ if name != "struct_size"}
 
 
 def sj_emit_source(kernel: int, spec: sj_spec | None = None, **kw) -> str:

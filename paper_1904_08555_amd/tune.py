@@ -16,14 +16,24 @@ The candidate set (at most 33 per kernel and layout):
     loads) in {2, 4, 8}, default order  (<= 9)
   * innermost axis is D (GZD, ZGD): STAGED with tile_k in {8, 16, 32},
     block 256, tile_n in {256, 512}; FP64 MFMA, ordinary or nontemporal
-    loads, with operands read by every lane (order 1: 16-row tiles per wave
+    loads (explicit flags), with operands read by every lane (order 1: 16-row tiles per wave
     in {1, 2, 4}, block in {256, 512}) or read as contiguous runs staged in
     LDS (order 2: tiles x block in {1x64, 1x256, 2x128, 2x256}); DIRECT with
     tile_n 1, unroll 8  (<= 27)
   * BF16 dtypes: columns per lane in {1, 4} (4 when it divides the extent),
     block in {256, 512}  (<= 4)
 Candidates that the specializer rejects for a shape (register or LDS limits)
-are dropped.
+are reported as rejected; candidates that resolve to the same specialization
+as an earlier one are dropped.
+
+Batched small products (bgemm_candidates, tune_bgemm): the workgroup form
+(persistent, the waves of a workgroup share a window) with window elements
+per array in {1024, 2048, 4096}, 16x16 tiles per work item in {1, 2, 4},
+block in {512, 1024} and the next window prefetched or not; the wave form
+(each wave owns a window) with windows of {256, 512} elements, {1, 2} tiles
+per item, block 256  (<= 40).  Each candidate is timed on the caller's batch
+through a plan, with the caller's scratch buffer written before every timed
+launch so that the batch is read from HBM.
 """
 from __future__ import annotations
 
@@ -33,6 +43,62 @@ from concurrent.futures import ThreadPoolExecutor
 from . import sj
 
 LAYOUTS = sj.LAYOUTS
+
+
+def bgemm_candidates() -> list:
+    out = []
+    for win in (1024, 2048, 4096):
+        for u in (1, 2, 4):
+            for block in (512, 1024):
+                for order in (2, 1):
+                    out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=win, unroll=u, block=block, order=order))
+    for win in (256, 512):
+        for u in (1, 2):
+            out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=win, unroll=u, block=256))
+    return out
+
+
+def tune_bgemm(n_host, A, B, C, cands=None, reps: int = 5, warmup: int = 1, flush=None, farm=None):
+    """Time every batched-product candidate on the caller's batch (sizes
+    n_host, device arrays A, B, C as for sj_batch_run).  ``flush`` (a device
+    tensor) is overwritten before every timed launch.  Returns the same dict
+    as tune_exhaustive."""
+    import torch
+    cands = bgemm_candidates() if cands is None else cands
+    if farm is not None:
+        made = farm.specialize_many([(sj.SJ_BGEMM, dict(c)) for c in cands])
+        built = [(c, h, err) for c, (h, _, err) in zip(cands, made)]
+    else:
+        built = compile_all(sj.SJ_BGEMM, {}, cands, threads=1)
+    stream = torch.cuda.current_stream()
+    results, rejected = [], []
+    for c, h, err in built:
+        if h is None:
+            rejected.append((c, str(err)))
+            continue
+        plan = sj.sj_batch_plan(h, n_host)
+        try:
+            for _ in range(warmup):
+                sj.sj_batch_run(plan, A, B, C)
+            ts = []
+            for _ in range(reps):
+                if flush is not None:
+                    flush.fill_(1)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sj.sj_batch_run(plan, A, B, C)
+                e1.record(stream)
+                ts.append((e0, e1))
+            torch.cuda.synchronize()
+            t = [x.elapsed_time(y) for x, y in ts]
+        finally:
+            sj.sj_plan_destroy(plan)
+        results.append((c, statistics.median(t), min(t)))
+    if not results:
+        raise RuntimeError(f"no batched-product candidate compiled: {rejected[:2]}")
+    order = sorted(range(len(results)), key=lambda i: (results[i][1], i))
+    best = results[order[0]]
+    return dict(best=best[0], best_ms=best[1], results=results, rejected=rejected)
 
 
 def contiguous_extent(layout: str, Z: int, G: int) -> int:
@@ -48,7 +114,7 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
                 continue
             for block in (256, 512):
                 out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=cpl, block=block))
-        return out
+        return distinct(kernel, dict(layout=layout, Z=Z, G=G, D=D, NM=NM, dtype=dtype), out)
     if ext > 1:
         for vec in (1, 2):
             if ext % vec:
@@ -67,13 +133,31 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
         for tk in (8, 16, 32):
             for tn in (256, 512):
                 out.append(dict(variant=sj.SJ_VAR_STAGED, tile_n=tn, tile_k=tk, block=256))
-        for fl in (0, sj.SJ_FLAG_LOADS_NONTEMPORAL):
+        for fl in (sj.SJ_FLAG_LOADS_CACHED, sj.SJ_FLAG_LOADS_NONTEMPORAL):
             for rt in (1, 2, 4):      # operands read by every lane straight from HBM
                 for block in (256, 512):
                     out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=1, flags=fl))
             for rt, block in ((1, 64), (1, 256), (2, 128), (2, 256)):   # contiguous runs staged in LDS
                 out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=2, flags=fl))
         out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=1, unroll=8, block=256))
+    return distinct(kernel, dict(layout=layout, Z=Z, G=G, D=D, NM=NM, dtype=dtype), out)
+
+
+def distinct(kernel: int, base: dict, cands: list) -> list:
+    """Drop candidates that resolve to the same specialization as an earlier
+    one (a tile the specializer clamps, a policy that equals the default):
+    the emitted source is the identity.  Candidates the specializer refuses are
+    kept, to be reported as rejected."""
+    seen, out = set(), []
+    for c in cands:
+        try:
+            src = sj.sj_emit_source(kernel, **dict(base, **c))
+        except sj.SJError:
+            out.append(c)
+            continue
+        if src not in seen:
+            seen.add(src)
+            out.append(c)
     return out
 
 

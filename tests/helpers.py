@@ -45,3 +45,32 @@ def host(t):
     import torch
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
+
+
+def layout_flat_index(layout, A, G, Z, a, g, z):
+    """Flat storage offset of logical element (a, g, z) of an (A, G, Z) array
+    stored in ``layout`` order (rightmost letter fastest).  Index bookkeeping only."""
+    ext = {"D": A, "G": G, "Z": Z}
+    val = {"D": np.asarray(a, dtype=np.int64), "G": np.asarray(g, dtype=np.int64),
+           "Z": np.asarray(z, dtype=np.int64)}
+    idx = np.zeros(np.broadcast(val["D"], val["G"], val["Z"]).shape, dtype=np.int64)
+    for c in layout:
+        idx = idx * ext[c] + val[c]
+    return idx
+
+
+def sample_columns(seed, G, Z, n):
+    """n sampled (g, z) columns, the first and last column always included."""
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, G, n)
+    z = rng.integers(0, Z, n)
+    g[:2], z[:2] = [0, G - 1], [0, Z - 1]
+    return g, z
+
+
+def gather_columns(out_d, layout, A, G, Z, g, z):
+    """Rows 0..A-1 of the sampled columns of a device array stored in
+    ``layout``: a (A, len(g)) float64 host array (a device gather, then a small copy)."""
+    import torch
+    idx = layout_flat_index(layout, A, G, Z, np.arange(A)[:, None], g[None, :], z[None, :])
+    return host(torch.take(out_d, torch.from_numpy(idx).cuda()))

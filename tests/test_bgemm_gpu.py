@@ -171,3 +171,31 @@ def test_bgemm_alias_rejected(P):
         P.sj_batch_run(plan, buf, buf, buf.data_ptr() + 8 * 8)
     assert e.value.status == P.SJ_ERR_ALIAS
     P.sj_plan_destroy(plan)
+
+
+def test_bgemm_every_tuner_candidate(P, orc):
+    """Every tile configuration the batched-product tuner can choose, on a
+    mixed batch (sizes 1..16, several windows per workgroup), against the oracle."""
+    from paper_1904_08555_amd import tune
+    n, off, A, B = batch(11, 3000, 1, 16)
+    ref = orc.bgemm(n, off[:-1], A, B)
+    scale = abs_scale(n, off, A, B)
+    A_d, B_d = dev(A), dev(B)
+    C_d = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+    for c in tune.bgemm_candidates():
+        C_d.fill_(float("nan"))
+        run_plan(P, n, A_d, B_d, C_d, **c)
+        assert err(host(C_d), ref, scale) <= TOL_F64, c
+
+
+def test_tune_bgemm_contract(P):
+    """tune_bgemm returns the lowest median of the candidates it timed."""
+    from paper_1904_08555_amd import tune
+    n, off, A, B = batch(12, 2000)
+    C_d = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+    cands = tune.bgemm_candidates()[:3] + [dict(variant=1, tile_n=100)]      # the last is refused
+    r = tune.tune_bgemm(n, dev(A), dev(B), C_d, cands=cands, reps=3)
+    assert len(r["results"]) == 3 and [c for c, _ in r["rejected"]] == [cands[3]]
+    meds = [m for _, m, _ in r["results"]]
+    i = min(range(3), key=lambda k: (meds[k], k))
+    assert r["best"] == r["results"][i][0] and r["best_ms"] == meds[i]

@@ -81,16 +81,23 @@ def test_mlp_training_reduces_loss(P):
     assert np.mean((pred - y) ** 2) < 0.3 * np.var(y)
 
 
+@pytest.mark.timeout(900)
 def test_picker_gain_small(P):
-    """A reduced picker experiment (small shapes, few samples): the trained
-    ensemble must land within a loose regret, not fall clearly behind the
-    untuned default (which is already close to the best for many shapes),
-    and its two best predictions must do at least as well as its first."""
+    """A reduced picker experiment (zones up to 24^3, three nestings, 640
+    training timings, 16 held-out shapes each timed over the exhaustive
+    tuner's whole candidate set).  What the trained network gains over the
+    method without it: against the exhaustive tuner, it compiles at most KMAX
+    candidates instead of all of them, at a small regret; against the untuned
+    default, its choice is faster; against a choice made without a model (a
+    random candidate), its regret is a fraction."""
     from paper_1904_08555_amd import picker
-    res, _ = picker.run_experiment(n_train_shapes=120, per_shape=4, n_eval=24, seed=3, workers=8, epochs=150,
-                                   log=lambda m: print(m, flush=True), max_k=24)
+    data = picker.collect(n_train_shapes=80, per_shape=8, n_eval=16, seed=3, workers=12, max_k=24,
+                          layouts=("DGZ", "GDZ", "ZGD"), log=lambda m: print(m, flush=True))
+    res, _, _ = picker.evaluate(data, seed=3, epochs=150, log=lambda m: print(m, flush=True))
     print(res)
-    assert res["eval_shapes"] >= 20
-    assert res["speedup_vs_default_geomean"] > 0.95
-    assert res["regret_mean"] < 0.5
-    assert res["top2_regret_mean"] <= res["regret_mean"]
+    assert res["eval_shapes"] >= 14
+    assert res["compiles_mean"] <= picker.KMAX and res["compiles_saved_frac"] >= 0.9
+    assert res["shortlist_regret_mean"] <= res["regret_mean"]
+    assert res["shortlist_regret_mean"] <= 0.15
+    assert res["regret_mean"] < 0.5 * res["random_choice_regret_mean"]
+    assert res["shortlist_speedup_vs_default_geomean"] > 1.0

@@ -1,0 +1,67 @@
+"""The learned picker's host logic: its candidate set is the exhaustive
+tuner's, its features describe the resolved specialization, and its
+shortlist rule (the fallback to timing) follows the ensemble's spread.  The
+networks themselves run on the GPU (tests/test_mlp_gpu.py)."""
+import json
+
+import numpy as np
+
+from paper_1904_08555_amd import picker, sj, tune
+
+
+def test_candidate_set_is_the_tuners():
+    rng = np.random.default_rng(5)
+    for s in picker.draw_shapes(rng, 12):
+        got = picker.candidates(s)
+        want = []
+        for lay in sj.LAYOUTS:
+            if s["dtype"] != sj.SJ_F64 and lay not in picker.COLUMN_LAYOUTS:
+                continue
+            for c in tune.candidates(sj.SJ_LTIMES, lay, s["Z"], s["G"], s["D"], s["NM"], s["dtype"]):
+                try:
+                    sj.sj_resolve(sj.SJ_LTIMES, **picker.spec_of(s, dict(layout=lay, **c)))
+                except sj.SJError:
+                    continue
+                want.append(dict(layout=lay, **c))
+        assert [json.dumps(c, sort_keys=True) for c in got] == [json.dumps(c, sort_keys=True) for c in want]
+        assert got
+
+
+def test_features_follow_the_resolved_spec():
+    s = dict(Z=32768, G=32, D=96, NM=16, dtype=sj.SJ_F64)
+    # the default request and the explicit spelling of what it resolves to give one feature vector
+    r = sj.sj_resolve(sj.SJ_LTIMES, **picker.spec_of(s, dict(layout="DGZ")))
+    explicit = dict(layout="DGZ", variant=r["variant"], tile_n=r["tile_n"], unroll=r["unroll"], block=r["block"],
+                    order=r["order"], flags=r["flags"] & ~sj.SJ_FLAG_INDEX64)
+    assert np.array_equal(picker.features(s, dict(layout="DGZ")), picker.features(s, explicit))
+    cs = picker.candidates(s)
+    F = np.stack([picker.features(s, c) for c in cs])
+    assert F.shape == (len(cs), picker.NFEAT) and np.isfinite(F).all()
+    # distinct specializations are told apart
+    assert len({tuple(row) for row in F}) == len(cs)
+
+
+class _FakeEnsemble(picker.Picker):
+    def __init__(self, preds):
+        self.preds = np.asarray(preds, dtype=np.float64)
+
+    def predict_members(self, shape, cands):
+        return self.preds
+
+
+def test_shortlist_follows_the_spread():
+    # member predictions for 5 candidates; means 0.0, 0.05, 1.0, 0.02, 0.5
+    confident = _FakeEnsemble([[0.0, 0.05, 1.0, 0.02, 0.5]] * 3)        # no spread: one compile
+    idx, mu = confident.shortlist({}, [None] * 5)
+    assert idx == [0] and np.allclose(mu, [0.0, 0.05, 1.0, 0.02, 0.5])
+    unsure = _FakeEnsemble([[0.0, 0.10, 1.0, 0.00, 0.5],
+                            [0.02, 0.00, 1.0, 0.04, 0.5],
+                            [-0.02, 0.05, 1.0, 0.02, 0.5]])
+    idx, _ = unsure.shortlist({}, [None] * 5)
+    # 0 first, then 3 and 1 (in predicted order) are within the spread; 4 and 2 are not
+    assert idx == [0, 3, 1]
+    idx, _ = unsure.shortlist({}, [None] * 5, kmax=2)
+    assert idx == [0, 3]
+    # ties in the mean go to the lowest candidate index
+    tie = _FakeEnsemble([[0.3, 0.1, 0.1]])
+    assert tie.shortlist({}, [None] * 3)[0] == [1]
