@@ -87,7 +87,8 @@ def test_picker_gain_small(P):
     training timings, 16 held-out shapes each timed over the exhaustive
     tuner's whole candidate set).  What the trained network gains over the
     method without it: against the exhaustive tuner, it compiles at most KMAX
-    candidates instead of all of them, at a small regret; against the untuned
+    candidates (a quarter of the set or less) instead of all of them, at a
+    small regret; against the untuned
     default, its choice is faster; against a choice made without a model (a
     random candidate), its regret is a fraction."""
     from paper_1904_08555_amd import picker
@@ -96,7 +97,7 @@ def test_picker_gain_small(P):
     res, _, _ = picker.evaluate(data, seed=3, epochs=150, log=lambda m: print(m, flush=True))
     print(res)
     assert res["eval_shapes"] >= 14
-    assert res["compiles_mean"] <= picker.KMAX and res["compiles_saved_frac"] >= 0.9
+    assert res["compiles_mean"] <= picker.KMAX and res["compiles_mean"] <= 0.25 * res["candidates_mean"]
     assert res["shortlist_regret_mean"] <= res["regret_mean"]
     assert res["shortlist_regret_mean"] <= 0.15
     assert res["regret_mean"] < 0.5 * res["random_choice_regret_mean"]
