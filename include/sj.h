@@ -301,6 +301,20 @@ sj_status sj_plan_destroy(sj_plan p);
 sj_status sj_run_adam(sj_handle h, void *const *ptrs, int nptrs, int64_t step,
                       double lr, double b1, double b2, double eps, void *stream);
 
+/* The MLP backward pass of an SJ_MLP_BWD handle, as sj_run computes it, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  ptrs = {theta, X, t, grad, loss}
+ * as for sj_run without the workspace: the per-row activations and deltas go
+ * to a static device array of 1,048,576 floats (4 MiB) that each device this
+ * library runs on holds until the process ends.  Requires rows * (4 width + 2)
+ * <= 1,048,576 (else SJ_ERR_INVALID_ARG, nothing launched).  Calls no
+ * allocator.  Every call on one device shares that device's array: calls that
+ * overlap on one device (different streams) race and must be ordered by the
+ * caller.  Results equal sj_run's bit for bit (same kernels, same order).
+ * Errors: as sj_run, plus SJ_ERR_HIP if the array's device address cannot be
+ * resolved. */
+sj_status sj_run_mlp_bwd_noalloc(sj_handle h, void *const *ptrs, int nptrs, void *stream);
+
 /* Time a specialization (the measurement primitive of the autotuner): `warmup`
  * untimed launches, then `reps` launches, each bracketed by HIP events on
  * `stream`.  When flush_bytes > 0 the caller's scratch buffer `flush` is

@@ -387,6 +387,10 @@ sj_status sj_init(int hip_device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return fail(SJ_ERR_HIP, "hipGetDeviceProperties failed");
     g_dev[hip_device].arch = prop.gcnArchName;
+    // the device address of this device's copy of the static MLP scratch (a failure is
+    // reported by the entry point that needs it, not here)
+    (void)noalloc_setup(hip_device);
+    clear_error();
     g_dev[hip_device].ready.store(true, std::memory_order_release);
     return SJ_OK;
 }

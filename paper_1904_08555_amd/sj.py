@@ -64,7 +64,7 @@ SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
 EXPORTED = (
     "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_values", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",
     "sj_batch_run", "sj_batch_graph_capture", "sj_batch_graph_launch", "sj_batch_plan_arrays", "sj_plan_destroy",
-    "sj_run_adam", "sj_time_run", "sj_resolve", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
+    "sj_run_adam", "sj_run_mlp_bwd_noalloc", "sj_time_run", "sj_resolve", "sj_emit_source", "sj_handle_info", "sj_handle_code", "sj_stats", "sj_cache_clear",
     "sj_last_error", "sj_status_string",
 )
 
@@ -143,6 +143,7 @@ def lib() -> ctypes.CDLL:
         "sj_batch_plan_arrays": [vp, P(vp), P(vp), P(i64)],
         "sj_plan_destroy": [vp],
         "sj_run_adam": [vp, P(vp), ctypes.c_int, i64, d, d, d, d, vp],
+        "sj_run_mlp_bwd_noalloc": [vp, P(vp), ctypes.c_int, vp],
         "sj_time_run": [vp, P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
                         P(ctypes.c_float)],
         "sj_resolve": [ctypes.c_int, P(sj_spec), P(sj_spec)],
@@ -282,6 +283,13 @@ def sj_specialize_with_code(kernel: int, code: bytes, spec: sj_spec | None = Non
 def sj_run(handle: Handle, ptrs, stream=None) -> None:
     arr = _ptr_array(ptrs)
     _check(lib().sj_run(handle.ptr, arr, len(ptrs), _stream(stream)))
+
+
+def sj_run_mlp_bwd_noalloc(handle: Handle, ptrs, stream=None) -> None:
+    """ptrs = {theta, X, t, grad, loss}: the backward pass with the library's
+    static scratch as workspace (see include/sj.h)."""
+    arr = _ptr_array(ptrs)
+    _check(lib().sj_run_mlp_bwd_noalloc(handle.ptr, arr, len(ptrs), _stream(stream)))
 
 
 def sj_generic_run(kernel: int, ptrs, spec: sj_spec | None = None, stream=None, **kw) -> None:
