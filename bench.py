@@ -658,7 +658,8 @@ def bench_batched(a):
 
 def bench_bf16(a):
     """LTimes, DGZ, Z=262144 G=64 D=128 NM=64: BF16 (psi FP32 in, phi FP32 out),
-    compensated BF16x3, and the FP64 path on the same values."""
+    compensated BF16x3, and the FP64 path on the same values; also both BF16
+    modes with D innermost (ZGD, the row form)."""
     import torch
 
     import paper_1904_08555_amd as P
@@ -686,6 +687,19 @@ def bench_bf16(a):
                          frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
                          vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"],
                          src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec))
+    # D innermost (ZGD): the row form, on the same logical values stored in that nesting
+    gdev.fill(psi32, 0, gen.ARR_PSI, gdev.DIST_U01_24, LAYOUTS.index("ZGD"), (D, G, Z))
+    for name, dt in (("bf16_zgd", P.SJ_BF16), ("bf16x3_zgd", P.SJ_BF16X3)):
+        spec = P.make_spec(layout="ZGD", Z=Z, G=G, D=D, NM=NM, dtype=dt)
+        h = P.sj_specialize(P.SJ_LTIMES, spec)
+        t = P.sj_time_run(h, [L_d, psi32, phi32], warmup=a.warmup, reps=a.steps)
+        ms = statistics.median(t)
+        info = P.sj_handle_info(h)
+        res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
+                         frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
+                         vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"],
+                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec))
+    gdev.fill(psi32, 0, gen.ARR_PSI, gdev.DIST_U01_24, 0, (D, G, Z))
     del phi32
     psi64 = psi32.to(torch.float64)
     del psi32

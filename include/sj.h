@@ -44,6 +44,10 @@
  *  - Outputs are overwritten (beta = 0).
  *  - Thread safety: sj_specialize compiles each key once even under concurrent
  *    calls; sj_run and the batch calls are reentrant.
+ *  - Logging: with SJ_LOG=1 in the environment, every specialization the
+ *    library builds (or fails to build) writes one line to stderr: kernel
+ *    name, key hash, device, emit / compile / load milliseconds, VGPRs, LDS,
+ *    scratch and code size.  Cache hits write nothing.
  */
 #ifndef SJ_H
 #define SJ_H
@@ -131,6 +135,16 @@ typedef enum sj_variant {
                                            for the spec's nesting (sizes still run-time arguments), Kripke's
                                            multiversioning; without it one kernel serves every nesting */
 #define SJ_FLAG_DEBUG_FAIL_COMPILE 0x100u /* test hook: the emitted source contains a failing static_assert */
+#define SJ_FLAG_XCD_CONTIGUOUS    0x200u /* LTimes / LPlusTimes / fused: workgroups are dispatched round-robin
+                                           over the device's 8 XCDs (each with its own L2); the kernel renumbers
+                                           them so that each XCD works through one contiguous range of the
+                                           columns (or of each sweep of a persistent grid) */
+#define SJ_FLAG_XCD_INTERLEAVED   0x400u /* LTimes / LPlusTimes / fused: workgroup b takes work item b (the
+                                           hardware's round-robin order) */
+/* Without an XCD flag the default measured on MI355X applies: contiguous for
+ * the kernels whose column axis is innermost (DIRECT, FP64 MFMA columns,
+ * BF16), interleaved for the row kernels (D innermost).  The two flags
+ * exclude each other and are part of the specialization key. */
 
 typedef struct sj_spec {
     uint32_t struct_size;   /* must be sizeof(sj_spec) */

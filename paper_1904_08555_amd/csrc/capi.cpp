@@ -16,6 +16,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -164,10 +165,44 @@ sj_status ensure_device(int *device, const char **arch)
     return SJ_OK;
 }
 
+// SJ_LOG=1 in the environment: one line per specialization built (or failed) on stderr.
+static bool log_enabled()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("SJ_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+static void log_build(const sj_handle_ &h, sj_status s, bool precompiled)
+{
+    if (!log_enabled()) return;
+    std::fprintf(stderr,
+                 "sj: %s %s key=%016llx device=%d emit=%.3f ms compile=%.3f ms load=%.3f ms vgprs=%d lds=%d "
+                 "scratch=%d code=%llu B%s\n",
+                 s == SJ_OK ? "built" : "FAILED", h.kernel_name.c_str(), (unsigned long long)h.hash, h.key.device,
+                 h.info.emit_ms, h.info.compile_ms, h.info.load_ms, h.info.vgprs, h.info.lds_bytes,
+                 h.info.scratch_bytes, (unsigned long long)h.code.size(), precompiled ? " (adopted code object)" : "");
+}
+
+static sj_status build_handle_impl(const SpecKey &key, const std::vector<char> *precompiled, const double *values,
+                                   sj_handle_ *h);
+
 static sj_status build_handle(const SpecKey &key, const std::vector<char> *precompiled, const double *values,
                               sj_handle_ **out)
 {
     auto h = std::make_unique<sj_handle_>();
+    const sj_status s = build_handle_impl(key, precompiled, values, h.get());
+    log_build(*h, s, precompiled != nullptr);
+    if (s != SJ_OK) return s;
+    *out = h.release();
+    return SJ_OK;
+}
+
+static sj_status build_handle_impl(const SpecKey &key, const std::vector<char> *precompiled, const double *values,
+                                   sj_handle_ *h)
+{
     h->key = key;
     h->hash = key_hash(key);
     std::memset(&h->info, 0, sizeof h->info);
@@ -248,7 +283,6 @@ static sj_status build_handle(const SpecKey &key, const std::vector<char> *preco
         g_stats.loads++;
         g_stats.load_ms_total += h->info.load_ms;
     }
-    *out = h.release();
     return SJ_OK;
 }
 

@@ -28,10 +28,21 @@ struct Strides {
     int z_fast;             // 1: consecutive threads take consecutive z
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); like the
+// specialized column kernels, the generic ones renumber them so that XCD x = b mod 8 takes one
+// contiguous range of columns (a bijection of the grid), so the comparison between the two does
+// not measure this launch order.
+__device__ __forceinline__ long long xcd_block()
+{
+    const unsigned b = blockIdx.x, n = gridDim.x;
+    const unsigned x = b % 8u, q = n / 8u, r = n % 8u;
+    return (long long)(x * q + (x < r ? x : r) + b / 8u);
+}
+
 __device__ __forceinline__ void ltimes_body(const double *__restrict__ L, const double *__restrict__ psi,
                                             double *__restrict__ phi, const Strides &s)
 {
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long t = xcd_block() * kBlock + threadIdx.x;
     if (t >= s.G * s.Z) return;
     long long g, z;
     if (s.z_fast) { g = t / s.Z; z = t - g * s.Z; }
@@ -60,7 +71,7 @@ __device__ __forceinline__ void ltimes_body(const double *__restrict__ L, const 
 __device__ __forceinline__ void lplustimes_body(const double *__restrict__ Lp, const double *__restrict__ phi,
                                                 double *__restrict__ out, const Strides &s)
 {
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long t = xcd_block() * kBlock + threadIdx.x;
     if (t >= s.G * s.Z) return;
     long long g, z;
     if (s.z_fast) { g = t / s.Z; z = t - g * s.Z; }
@@ -87,13 +98,15 @@ __device__ __forceinline__ void lplustimes_body(const double *__restrict__ Lp, c
 // `red` input values and a contiguous row of `outn` outputs, so N columns are
 // one [N][red] and one [N][outn] row-major matrix, W is [outn][red] row-major
 // (L for LTimes, L+ for LPlusTimes).  A workgroup takes `tr` consecutive rows
-// (tr chosen on the host so the tiles fit in dynamic LDS): it reads them as one
-// contiguous run (consecutive threads, consecutive addresses) into LDS with a
-// row pitch of red + 1, each thread then forms outputs of one row in register
-// chunks of 16 (outputs j, j + kBlock/tr, ...), and the [tr][outn] results leave
-// through LDS as one contiguous run.  Only the loop bounds and addresses are
-// run-time values; the access pattern is the coalesced one a specialization
-// uses, so the comparison measures what compile-time sizes buy.
+// (tr chosen on the host so that the tiles fit in dynamic LDS): it reads them
+// as one contiguous run (consecutive threads, consecutive addresses) into LDS
+// with a row pitch of red + 1, W into LDS beside them when it fits (else W is
+// read through the caches), each thread then forms outputs of one row in
+// register chunks of 16 (outputs j, j + kBlock/tr, ...), and the [tr][outn]
+// results leave through LDS as one contiguous run.  Only the loop bounds and
+// addresses are run-time values; the access pattern is the coalesced one a
+// specialization uses, so the comparison measures what compile-time sizes buy.
+template <bool WLDS>
 __global__ void __launch_bounds__(kBlock)
 generic_rows(const double *__restrict__ W, const double *__restrict__ in, double *__restrict__ out, long long N,
              long long red, long long outn, int tr)
@@ -101,52 +114,85 @@ generic_rows(const double *__restrict__ W, const double *__restrict__ in, double
     extern __shared__ double lds[];
     double *xin = lds;                                   // [tr][red + 1]
     double *yout = lds + (long long)tr * (red + 1);      // [tr][outn + 1]
+    double *wl = yout + (long long)tr * (outn + 1);      // [outn][red] when WLDS
     const long long r0 = (long long)blockIdx.x * tr;
-    const long long rows = N - r0 < tr ? N - r0 : tr;
-    const long long nin = rows * red, nout = rows * outn;
+    const int rows = (int)(N - r0 < tr ? N - r0 : tr);
+    // tile-local indices fit in 32 bits (the tiles are within 64 KiB); element e = row r, column c is
+    // advanced by kBlock without a division per element
+    const int ired = (int)red, iout = (int)outn;
+    const int nin = rows * ired, nout = rows * iout;
     const double *src = in + r0 * red;
-    for (long long e = threadIdx.x; e < nin; e += kBlock) {
-        const long long r = e / red;
-        xin[r * (red + 1) + (e - r * red)] = src[e];
+    {
+        // eight loads in flight per thread before their LDS writes
+        constexpr int U = 8;
+        int r = (int)threadIdx.x / ired, c = (int)threadIdx.x % ired;
+        const int dr = kBlock / ired, dc = kBlock % ired;
+        for (int e0 = threadIdx.x; e0 < nin; e0 += U * kBlock) {
+            double v[U];
+            int at[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kBlock;
+                at[u] = r * (ired + 1) + c;
+                v[u] = e < nin ? src[e] : 0.0;
+                r += dr;
+                c += dc;
+                if (c >= ired) { c -= ired; ++r; }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * kBlock < nin) xin[at[u]] = v[u];
+        }
     }
+    if (WLDS)
+        for (int e = threadIdx.x; e < iout * ired; e += kBlock) wl[e] = W[e];
     __syncthreads();
+    const double *Wr = WLDS ? wl : W;
     const int per = kBlock / tr;                         // threads per row
     const int r = threadIdx.x % tr, j0 = threadIdx.x / tr;
     if (r < rows && j0 < per) {
-        const double *x = xin + (long long)r * (red + 1);
-        for (long long o0 = j0; o0 < outn; o0 += (long long)per * kChunk) {
+        const double *x = xin + r * (ired + 1);
+        for (int o0 = j0; o0 < iout; o0 += per * kChunk) {
             double acc[kChunk];
             const double *wr[kChunk];
 #pragma unroll
             for (int c = 0; c < kChunk; ++c) {
                 acc[c] = 0.0;
-                const long long o = o0 + (long long)c * per;
-                wr[c] = W + (o < outn ? o : outn - 1) * red;   // past outn: repeat the last row, never stored
+                const int o = o0 + c * per;
+                wr[c] = Wr + (long long)(o < iout ? o : iout - 1) * red;   // past outn: repeat the last row, never stored
             }
-            for (long long k = 0; k < red; ++k) {
+            for (int k = 0; k < ired; ++k) {
                 const double xv = x[k];
 #pragma unroll
                 for (int c = 0; c < kChunk; ++c) acc[c] = __builtin_fma(wr[c][k], xv, acc[c]);
             }
 #pragma unroll
             for (int c = 0; c < kChunk; ++c) {
-                const long long o = o0 + (long long)c * per;
-                if (o < outn) yout[(long long)r * (outn + 1) + o] = acc[c];
+                const int o = o0 + c * per;
+                if (o < iout) yout[r * (iout + 1) + o] = acc[c];
             }
         }
     }
     __syncthreads();
     double *dst = out + r0 * outn;
-    for (long long e = threadIdx.x; e < nout; e += kBlock) {
-        const long long rr = e / outn;
-        dst[e] = yout[rr * (outn + 1) + (e - rr * outn)];
+    {
+        int rr = (int)threadIdx.x / iout, c = (int)threadIdx.x % iout;
+        const int dr = kBlock / iout, dc = kBlock % iout;
+        for (int e = threadIdx.x; e < nout; e += kBlock) {
+            dst[e] = yout[rr * (iout + 1) + c];
+            rr += dr;
+            c += dc;
+            if (c >= iout) { c -= iout; ++rr; }
+        }
     }
 }
 
-// Rows per workgroup of generic_rows: both tiles within 64 KiB of LDS.
-inline int generic_rows_tile(long long red, long long outn)
+// Rows per workgroup of generic_rows: the row tiles (and W, when it is staged)
+// within 64 KiB of LDS.
+inline int generic_rows_tile(long long red, long long outn, bool wlds)
 {
-    const long long t = 8192 / (red + outn + 2);
+    const long long room = 8192 - (wlds ? outn * red : 0);
+    const long long t = room / (red + outn + 2);
     return (int)std::max<long long>(1, std::min<long long>(kBlock, t));
 }
 
@@ -285,13 +331,19 @@ extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *cons
         double *outp = (double *)ptrs[2];
         if (st_.ad == 1 && st_.bd == 1 && A_in + A_out + 2 <= 8192) {
             // the reduction axis is innermost in both arrays: rows staged through LDS (serves the
-            // generic call and the per-nesting one alike: the access pattern is the nesting's)
-            const int tr = generic_rows_tile(A_in, A_out);
+            // generic call and the per-nesting one alike: the access pattern is the nesting's); W
+            // is staged too when that still leaves room for 32 rows
+            const bool wlds = A_in * A_out + 32 * (A_in + A_out + 2) <= 8192;
+            const int tr = generic_rows_tile(A_in, A_out, wlds);
             const long long nrow = ((long long)cols + tr - 1) / tr;
             if (nrow > 2147483647LL) return fail(SJ_ERR_UNSUPPORTED, "too many columns for one launch");
-            const size_t shm = (size_t)tr * (size_t)(A_in + A_out + 2) * 8;
-            hipLaunchKernelGGL(generic_rows, dim3((unsigned)nrow), dim3(kBlock), shm, st, L, in, outp,
-                               (long long)cols, A_in, A_out, tr);
+            const size_t shm = ((size_t)tr * (size_t)(A_in + A_out + 2) + (wlds ? (size_t)(A_in * A_out) : 0)) * 8;
+            if (wlds)
+                hipLaunchKernelGGL(generic_rows<true>, dim3((unsigned)nrow), dim3(kBlock), shm, st, L, in, outp,
+                                   (long long)cols, A_in, A_out, tr);
+            else
+                hipLaunchKernelGGL(generic_rows<false>, dim3((unsigned)nrow), dim3(kBlock), shm, st, L, in, outp,
+                                   (long long)cols, A_in, A_out, tr);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
             return SJ_OK;

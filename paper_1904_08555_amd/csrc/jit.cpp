@@ -184,7 +184,12 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     std::snprintf(key.arch, sizeof key.arch, "%s", arch ? arch : "");
     key.flags = s->flags & (SJ_FLAG_COMPILE_ONLY | SJ_FLAG_DEBUG_FAIL_COMPILE | SJ_FLAG_LOADS_CACHED |
                             SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED | SJ_FLAG_STORES_NONTEMPORAL |
-                            SJ_FLAG_ACCUMULATE);
+                            SJ_FLAG_ACCUMULATE | SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
+    if ((s->flags & SJ_FLAG_XCD_CONTIGUOUS) && (s->flags & SJ_FLAG_XCD_INTERLEAVED))
+        return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_XCD_CONTIGUOUS and SJ_FLAG_XCD_INTERLEAVED exclude each other");
+    if ((s->flags & (SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED)) && k != SJ_LTIMES && k != SJ_LPLUSTIMES &&
+        k != SJ_LTIMES_LPLUS)
+        return fail(SJ_ERR_INVALID_ARG, "the XCD flags apply to LTimes, LPlusTimes and the fused kernel");
     if ((s->flags & SJ_FLAG_ACCUMULATE) && k != SJ_LTIMES && k != SJ_LPLUSTIMES)
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_ACCUMULATE applies to LTimes and LPlusTimes");
     if (k == SJ_LTIMES_LPLUS) {
@@ -399,16 +404,21 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             key.tile_k = 16;
             key.full_unroll = 1;
         } else {
-            // BF16 matrix-core LTimes, column axis contiguous: one 32-column tile per wave.
-            if (key.I == 1) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes needs a layout with a column axis innermost");
+            // BF16 matrix-core LTimes: column axis contiguous, a 32- or 128-column tile per wave; D
+            // innermost (GZD, ZGD), a 32-row tile per wave (tile_n 1; D % 4 == 0 for 16-byte rows).
             if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "this structure has no order 2");
             key.order = 1;
             key.block = s->block ? s->block : 256;
             if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            if (key.I == 1) {
+                if (s->D % 4 != 0) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes with D innermost needs D % 4 == 0");
+                if (s->tile_n != 0 && s->tile_n != 1)
+                    return fail(SJ_ERR_INVALID_ARG, "BF16 LTimes with D innermost takes tile_n 1 (32 rows per wave)");
+            }
             // tile_n = columns per lane: 1 (4-byte loads, 32 columns per wave) or 4 (16-byte loads,
             // 128 columns per wave as four interleaved MFMA tiles; needs the column extent % 4 == 0).
             int cpl = s->tile_n;
-            if (cpl == 0) cpl = (key.I % 4 == 0 && key.block <= 512) ? 4 : 1;
+            if (cpl == 0) cpl = (key.I > 1 && key.I % 4 == 0 && key.block <= 512) ? 4 : 1;
             if (cpl != 1 && cpl != 4) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n (columns per lane) must be 1 or 4");
             if (cpl == 4 && key.I % 4 != 0) return fail(SJ_ERR_INVALID_ARG, "BF16 tile_n 4 needs a column extent divisible by 4");
             // four columns per lane hold 128 FP32 accumulators: a 1024-thread block leaves 128 registers
@@ -433,6 +443,9 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
                        SJ_FLAG_STORES_NONTEMPORAL);
         key.flags |= (ntl ? SJ_FLAG_LOADS_NONTEMPORAL : SJ_FLAG_LOADS_CACHED) |
                      (nts ? SJ_FLAG_STORES_NONTEMPORAL : SJ_FLAG_STORES_CACHED);
+        const bool xcd = xcd_contiguous(key);
+        key.flags &= ~(SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
+        key.flags |= xcd ? SJ_FLAG_XCD_CONTIGUOUS : SJ_FLAG_XCD_INTERLEAVED;
         return (*out = key), SJ_OK;
     }
     if (k == SJ_MASS) {
@@ -444,24 +457,46 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (s->count < 1 || s->count > (int64_t(1) << 31) - 1) return fail(SJ_ERR_INVALID_ARG, "count (elements) must be in [1, 2^31-1]");
         if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
             return fail(SJ_ERR_UNSUPPORTED, "the mass operator has the DIRECT structure only");
-        if (s->tile_k != 0 || s->unroll != 0 || (s->order != 0 && s->order != 1) || (s->flags & SJ_FLAG_ACCUMULATE))
-            return fail(SJ_ERR_INVALID_ARG, "the mass operator takes tile_n and block only");
+        if (s->tile_k != 0 || s->unroll != 0 || s->order < 0 || s->order > 2 || (s->flags & SJ_FLAG_ACCUMULATE))
+            return fail(SJ_ERR_INVALID_ARG, "the mass operator takes tile_n, block and order (0, 1, 2) only");
+        // order 1: one group of elements per wave, x and D staged in LDS; order 2: persistent waves
+        // that load the next group into registers while computing the current one (D stays in
+        // registers)
+        int order = s->order;
         const int64_t dim = s->inputs, D1D = s->D, Q1D = s->NM, mx = std::max(D1D, Q1D);
         int64_t nd = 1, nq = 1, ns = 1, mxlo = 1;
         for (int64_t i = 0; i < dim; ++i) { nd *= D1D; nq *= Q1D; ns *= mx; }
         for (int64_t i = 0; i + 1 < dim; ++i) mxlo *= mx;
         // elements per wave: measured on MI355X at D1D=4 Q1D=6, hexahedra 1 (441 us; 2: 550 us),
         // quadrilaterals 4 (276 us; 10: 335 us): about 24 pencils in the widest contraction
-        int ew = s->tile_n ? s->tile_n : (int)std::max<int64_t>(1, std::min<int64_t>(32, 24 / mxlo));
+        // The pipelined form (order 2) holds a group's x and two groups' D values per lane in
+        // registers: nlx + 2 nld doubles.  Defaults measured on MI355X (500,000 hexahedra and
+        // 2,000,000 quadrilaterals, D1D=4 Q1D=6): pipelined with the largest group of at most 8
+        // elements whose registers stay within 40 doubles (hexahedra 4: 274 us, 1: 368 us;
+        // quadrilaterals 8: 209 us, 4: 242 us), 64-thread workgroups; where even one element
+        // exceeds that, the staged form with about 24 pencils in the widest contraction (the
+        // pipelined form spills beyond about 90 doubles).
+        auto regs = [&](int64_t e) { return (e * nd + 63) / 64 + 2 * ((e * nq + 63) / 64); };
+        int ew = s->tile_n;
+        if (ew == 0) {
+            if (order != 1 && regs(1) <= 40) {
+                ew = 1;
+                while (ew < 8 && regs(2 * ew) <= 40) ew *= 2;
+                if (order == 0) order = 2;
+            } else {
+                ew = (int)std::max<int64_t>(1, std::min<int64_t>(32, 24 / mxlo));
+            }
+        }
         if (ew < 1 || ew > 64) return fail(SJ_ERR_INVALID_ARG, "tile_n (elements per wave) must be in [1, 64]");
-        auto lds = [&](int block) { return (int64_t)(block / 64) * ew * (2 * ns + nq) * 8; };
+        if (order == 0) order = (regs(ew) <= 40) ? 2 : 1;
+        auto lds = [&](int block) { return (int64_t)(block / 64) * ew * (2 * ns + (order == 1 ? nq : 0)) * 8; };
         int block = s->block;
-        if (block == 0) block = (lds(128) <= 64 * 1024) ? 128 : 64;
+        if (block == 0) block = (order == 2) ? 64 : (lds(128) <= 64 * 1024) ? 128 : 64;
         if (!valid_block(block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
         if (lds(block) > 160 * 1024) return fail(SJ_ERR_UNSUPPORTED, "mass operator tiles exceed 160 KiB of LDS");
         if (s->count * std::max(nd, nq) > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "arrays too large");
         key.D = D1D; key.NM = Q1D; key.inputs = dim; key.rows = s->count;
-        key.tile_n = ew; key.block = block; key.variant = SJ_VAR_DIRECT; key.order = 1;
+        key.tile_n = ew; key.block = block; key.variant = SJ_VAR_DIRECT; key.order = order;
         key.index64 = (s->count * std::max(nd, nq) >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
         return (*out = key), SJ_OK;
     }
@@ -632,6 +667,10 @@ Geometry key_geometry(const SpecKey &k)
     if (k.kernel == SJ_MASS) {
         const int64_t per_block = (int64_t)(k.block / 64) * k.tile_n;
         g.grid = (unsigned)((k.rows + per_block - 1) / per_block);
+        if (k.order == 2) {   // persistent: capped at load time to the workgroups the device holds at once
+            g.grid = (unsigned)std::min<int64_t>(g.grid, 65536);
+            g.persistent = 1;
+        }
     }
     if (k.kernel == SJ_LTIMES || k.kernel == SJ_LPLUSTIMES || k.kernel == SJ_LTIMES_LPLUS) {
         if (k.variant == SJ_VAR_DIRECT) {
@@ -660,7 +699,7 @@ Geometry key_geometry(const SpecKey &k)
             g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
         } else if (k.variant == SJ_VAR_MFMA) {
             const int64_t cols = k.tile_n == 4 ? 128 : 32;
-            const int64_t tiles = k.B * ((k.I + cols - 1) / cols);
+            const int64_t tiles = k.I == 1 ? (k.B + 31) / 32 : k.B * ((k.I + cols - 1) / cols);
             const int64_t waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
         }
@@ -669,6 +708,22 @@ Geometry key_geometry(const SpecKey &k)
 }
 
 // ---------------------------------------------------------------- emission
+
+// contraction kernels: the workgroup renumbering for XCD-contiguous work
+static const char *kXcdHelper =
+    "// Workgroups are dispatched round-robin over the XCDs (each with its own L2).  With SJ_XCD > 1,\n"
+    "// workgroup b works as logical block sj_block_id(): XCD x = b mod SJ_XCD takes one contiguous\n"
+    "// range of logical blocks (a bijection of [0, gridDim.x) for any grid size).\n"
+    "__device__ __forceinline__ unsigned sj_block_id()\n"
+    "{\n"
+    "#if SJ_XCD > 1\n"
+    "    const unsigned b = blockIdx.x, n = gridDim.x;\n"
+    "    const unsigned x = b % SJ_XCD, q = n / SJ_XCD, r = n % SJ_XCD;\n"
+    "    return x * q + (x < r ? x : r) + b / SJ_XCD;\n"
+    "#else\n"
+    "    return blockIdx.x;\n"
+    "#endif\n"
+    "}\n";
 
 static const char *kCommonPrologue =
     "// emitted by the sj specializer\n"
@@ -709,6 +764,16 @@ void load_store_policy(const SpecKey &k, int *nt_load, int *nt_store)
     *nt_store = nts;
 }
 
+bool xcd_contiguous(const SpecKey &k)
+{
+    // explicit flags, else the default measured on MI355X at Z=32768 G=32 D=96 NM=16 with an
+    // access-pattern probe of the column kernels (96 rows 8 MiB apart, two columns per thread):
+    // 197 us in the hardware's round-robin order, 157 us with each XCD on a contiguous column range
+    if (k.flags & SJ_FLAG_XCD_CONTIGUOUS) return true;
+    if (k.flags & SJ_FLAG_XCD_INTERLEAVED) return false;
+    return k.I > 1 && k.variant != SJ_VAR_STAGED;
+}
+
 // The templates name their kernel through this macro.
 static const char *base_name_macro(const SpecKey &) { return "SJ_KERNEL_NAME"; }
 
@@ -729,7 +794,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         int ntl = 0, nts = 0;
         load_store_policy(k, &ntl, &nts);
         o << "#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM "
-          << ((k.flags & SJ_FLAG_ACCUMULATE) ? 1 : 0) << "\n";
+          << ((k.flags & SJ_FLAG_ACCUMULATE) ? 1 : 0) << "\n#define SJ_XCD " << (xcd_contiguous(k) ? 8 : 0) << "\n"
+          << kXcdHelper;
         if (k.variant == SJ_VAR_DIRECT) {
             o << "#define SJ_VEC " << k.tile_n << "\n#define SJ_UNROLL " << k.unroll << "\n#define SJ_FULL_UNROLL "
               << k.full_unroll << "\n#define SJ_ROTATE " << (k.order == 2 ? 1 : 0) << "\n";
@@ -778,9 +844,10 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
             }
         } else if (k.variant == SJ_VAR_MFMA) {
             *name = (k.dtype == SJ_BF16X3) ? "sj_ltimes_bf16x3" : "sj_ltimes_bf16";
-            if (k.tile_n == 4) *name += "w";
+            if (k.I == 1) *name += "_rows";
+            else if (k.tile_n == 4) *name += "w";
             o << "#define SJ_X3 " << (k.dtype == SJ_BF16X3 ? 1 : 0) << "\n";
-            body = (k.tile_n == 4) ? kTpl_ltimes_bf16w : kTpl_ltimes_bf16;
+            body = (k.I == 1) ? kTpl_ltimes_bf16_rows : (k.tile_n == 4) ? kTpl_ltimes_bf16w : kTpl_ltimes_bf16;
         }
     }
     if (k.kernel == SJ_MASS) {
@@ -788,8 +855,9 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
           << k.rows << sfx << "\n#define SJ_EW " << k.tile_n << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD "
           << ((k.flags & SJ_FLAG_LOADS_CACHED) ? 0 : 1) << "\n#define SJ_NT_STORE " << ((k.flags & SJ_FLAG_STORES_CACHED) ? 0 : 1)
           << "\n#define SJ_ACCUM 0\n";
-        body = kTpl_mass_pa;
-        *name = "sj_mass_pa_" + std::to_string(k.inputs) + "d_d" + std::to_string(k.D) + "_q" + std::to_string(k.NM);
+        body = (k.order == 2) ? kTpl_mass_pa_pipe : kTpl_mass_pa;
+        *name = std::string(k.order == 2 ? "sj_mass_pa_pipe_" : "sj_mass_pa_") + std::to_string(k.inputs) + "d_d" +
+                std::to_string(k.D) + "_q" + std::to_string(k.NM);
         o << "#define SJ_KERNEL_NAME " << *name << "\n";
     }
     if (k.kernel == SJ_SCATTERING) {

@@ -67,6 +67,10 @@ inline int64_t mlp_nparams(int64_t inputs, int64_t width) { return width * input
 // else the measured defaults.
 void load_store_policy(const SpecKey &key, int *nt_load, int *nt_store);
 
+// Whether a contraction key renumbers its workgroups so that each XCD takes a
+// contiguous range (explicit SJ_FLAG_XCD_* flags, else the measured default).
+bool xcd_contiguous(const SpecKey &key);
+
 // Launch geometry of a resolved key.
 struct Geometry {
     unsigned grid;

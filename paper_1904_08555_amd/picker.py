@@ -4,8 +4,7 @@ The exhaustive autotuner (tune.py) compiles and times every candidate
 specialization of a shape; the picker predicts each candidate's run time
 relative to the shape's other candidates and compiles only what it cannot rule
 out.  The candidate set of a shape s is exactly the tuner's: C(s) = the union
-over nestings of tune.candidates(LTimes, nesting, s) (every nesting for FP64,
-the column-innermost ones for BF16x3), so the tuner's best over C(s) is both
+over nestings of tune.candidates(LTimes, nesting, s), so the tuner's best over C(s) is both
 the judge of the picker's regret and its fallback.
 
 Model: five networks (features -> 64 -> 64 -> 1, ReLU, FP32, different seeds);
@@ -42,7 +41,7 @@ from . import sj, tune
 
 LAYOUTS = sj.LAYOUTS
 COLUMN_LAYOUTS = ("DGZ", "DZG", "GDZ", "ZDG")
-NFEAT = 36
+NFEAT = 37
 WIDTH = 64
 TAU = 1.0      # spread multiple within which two predictions are not told apart
 KMAX = 4       # at most this many candidates compiled and timed per shape
@@ -60,11 +59,10 @@ def contiguous_extent(layout: str, Z: int, G: int) -> int:
 
 
 def candidates(shape: dict, layouts=None) -> list:
-    """C(s): the exhaustive tuner's candidates over every nesting the dtype
-    supports (restricted to ``layouts`` when given), each tagged with its
-    nesting; candidates the specializer refuses for the shape are left out."""
-    f64 = shape["dtype"] == sj.SJ_F64
-    lays = [l for l in (layouts or LAYOUTS) if f64 or l in COLUMN_LAYOUTS]
+    """C(s): the exhaustive tuner's candidates over every nesting (restricted
+    to ``layouts`` when given), each tagged with its nesting; candidates the
+    specializer refuses for the shape are left out."""
+    lays = list(layouts or LAYOUTS)
     out = []
     for lay in lays:
         for c in tune.candidates(sj.SJ_LTIMES, lay, shape["Z"], shape["G"], shape["D"], shape["NM"],
@@ -139,7 +137,8 @@ def features(shape: dict, cand: dict) -> np.ndarray:
     f[32] = math.log2(max(1.0, G * Z / max(1, width)))    # lanes of work
     f[33] = 1.0 if r["flags"] & sj.SJ_FLAG_INDEX64 else 0.0
     f[34] = math.log2(2.0 * D * NM * G * Z) - math.log2((D + NM) * G * Z * esz)  # arithmetic intensity
-    f[35] = 1.0
+    f[35] = 1.0 if r["flags"] & sj.SJ_FLAG_XCD_CONTIGUOUS else 0.0
+    f[36] = 1.0
     return f
 
 

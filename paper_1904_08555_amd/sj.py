@@ -60,6 +60,8 @@ SJ_FLAG_STORES_NONTEMPORAL = 0x20
 SJ_FLAG_ACCUMULATE = 0x40
 SJ_FLAG_GENERIC_PER_LAYOUT = 0x80
 SJ_FLAG_DEBUG_FAIL_COMPILE = 0x100
+SJ_FLAG_XCD_CONTIGUOUS = 0x200
+SJ_FLAG_XCD_INTERLEAVED = 0x400
 
 EXPORTED = (
     "sj_init", "sj_layout_from_string", "sj_specialize", "sj_specialize_values", "sj_specialize_with_code", "sj_run", "sj_generic_run", "sj_batch_plan",

@@ -7,7 +7,7 @@ runs), times each one with sj_time_run, and returns the fastest together with
 every timing.  This is the profile-guided autotuning named as future work in
 ClangJIT section 6; it is also the reference the learned picker is measured against.
 
-The candidate set (at most 33 per kernel and layout):
+The candidate set (at most 35 per kernel and layout):
   * innermost axis is a column axis (DGZ, DZG, GDZ, ZDG):
     DIRECT with tile_n (columns per thread) in {1, 2} dividing the contiguous
     extent, unroll in {4, 8, 16}, block in {256, 512}, order in {ascending,
@@ -18,8 +18,9 @@ The candidate set (at most 33 per kernel and layout):
     block 256, tile_n in {256, 512}; FP64 MFMA, ordinary or nontemporal
     loads (explicit flags), with operands read by every lane (order 1: 16-row tiles per wave
     in {1, 2, 4}, block in {256, 512}) or read as contiguous runs staged in
-    LDS (order 2: tiles x block in {1x64, 1x256, 2x128, 2x256}); DIRECT with
-    tile_n 1, unroll 8  (<= 27)
+    LDS (order 2: tiles x block in {1x64, 1x256, 2x128, 2x256}, workgroups in
+    the hardware's XCD order or renumbered so that each XCD takes a contiguous
+    range of each sweep); DIRECT with tile_n 1, unroll 8  (<= 35)
   * BF16 dtypes: columns per lane in {1, 4} (4 when it divides the extent),
     block in {256, 512}  (<= 4)
 Candidates that the specializer rejects for a shape (register or LDS limits)
@@ -138,7 +139,8 @@ def candidates(kernel: int, layout: str, Z: int, G: int, D: int, NM: int, dtype:
                 for block in (256, 512):
                     out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=1, flags=fl))
             for rt, block in ((1, 64), (1, 256), (2, 128), (2, 256)):   # contiguous runs staged in LDS
-                out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=2, flags=fl))
+                for xcd in (sj.SJ_FLAG_XCD_INTERLEAVED, sj.SJ_FLAG_XCD_CONTIGUOUS):
+                    out.append(dict(variant=sj.SJ_VAR_MFMA, tile_n=rt, block=block, order=2, flags=fl | xcd))
         out.append(dict(variant=sj.SJ_VAR_DIRECT, tile_n=1, unroll=8, block=256))
     return distinct(kernel, dict(layout=layout, Z=Z, G=G, D=D, NM=NM, dtype=dtype), out)
 

@@ -48,17 +48,18 @@ def run_bf16(P, dtype, layout, Z, G, D, NM, L_d, psi_d, **tile):
     return phi_d
 
 
-SHAPES = [(37, 5, 11, 6), (300, 3, 48, 16), (64, 2, 128, 64), (1, 33, 7, 40), (96, 4, 96, 16), (5, 7, 250, 3)]
+SHAPES = [(37, 5, 11, 6), (300, 3, 48, 16), (64, 2, 128, 64), (1, 33, 7, 40), (96, 4, 96, 16), (5, 7, 250, 3),
+          (37, 5, 12, 6), (1, 33, 20, 40), (5, 7, 252, 3), (33, 1, 16, 33), (3, 3, 4, 1)]
 
 
-@pytest.mark.parametrize("layout", ["DGZ", "DZG", "GDZ", "ZDG"])
+@pytest.mark.parametrize("layout", ["DGZ", "DZG", "GDZ", "ZDG", "GZD", "ZGD"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "Z%dG%dD%dNM%d" % s)
 def test_bf16_bounds(P, orc, layout, shape):
     Z, G, D, NM = shape
-    if {"DGZ": G * Z, "DZG": G * Z, "GDZ": Z, "ZDG": G}[layout] == 1:
+    if {"DGZ": G * Z, "DZG": G * Z, "GDZ": Z, "ZDG": G}.get(layout, 1) == 1 and D % 4 != 0:
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_LTIMES, layout=layout, Z=Z, G=G, D=D, NM=NM, dtype=P.SJ_BF16)
-        assert e.value.status == P.SJ_ERR_UNSUPPORTED   # contiguous extent 1: no column axis to vectorize
+        assert e.value.status == P.SJ_ERR_UNSUPPORTED   # rows of D values read as 16-byte pieces: D % 4 == 0
         return
     L, psi = bf16_inputs(2, layout, Z, G, D, NM)
     exact = orc.ltimes(layout, Z, G, D, NM, L, psi)
@@ -99,10 +100,45 @@ def test_bf16_block_sizes(P, orc):
         assert componentwise_err(got, exact, scale) <= 3 * UB * UB + gs(3 * D + 1)
 
 
-def test_bf16_d_innermost_unsupported(P):
+def test_bf16_d_innermost_limits(P):
+    """With D innermost the rows are read in 16-byte pieces: D % 4 != 0 is
+    refused, and the row form takes no other tile than one 32-row tile per wave."""
     with pytest.raises(P.SJError) as e:
-        P.sj_specialize(P.SJ_LTIMES, layout="GZD", Z=4, G=2, D=8, NM=4, dtype=P.SJ_BF16)
+        P.sj_specialize(P.SJ_LTIMES, layout="GZD", Z=4, G=2, D=10, NM=4, dtype=P.SJ_BF16)
     assert e.value.status == P.SJ_ERR_UNSUPPORTED
+    with pytest.raises(P.SJError) as e:
+        P.sj_specialize(P.SJ_LTIMES, layout="ZGD", Z=4, G=2, D=8, NM=4, dtype=P.SJ_BF16, tile_n=4)
+    assert e.value.status == P.SJ_ERR_INVALID_ARG
+    h = P.sj_specialize(P.SJ_LTIMES, layout="ZGD", Z=4, G=2, D=8, NM=4, dtype=P.SJ_BF16X3)
+    assert P.sj_handle_info(h)["kernel_name"].startswith("sj_ltimes_bf16x3_rows")
+
+
+@pytest.mark.parametrize("layout", ["GZD", "ZGD"])
+def test_bf16_rows_large_sampled(P, orc, layout):
+    """D innermost at Z=262144 G=64 D=128 NM=64 (psi 8.6 GB FP32): both modes,
+    1024 sampled columns against the oracle and the stated bounds."""
+    from helpers import gather_columns, sample_columns
+    Z, G, D, NM = 262144, 64, 128, 64
+    li = gen.LAYOUTS.index(layout)
+    psi_d = torch.empty(D * G * Z, dtype=torch.float32, device="cuda")
+    gdev.fill(psi_d, 0, gen.ARR_PSI, gdev.DIST_U01_24, li, (D, G, Z))
+    L = gen.matrix_sym(0, gen.ARR_L, NM, D)
+    g, z = sample_columns(7 + li, G, Z, 1024)
+    cols = gen.psi_columns(0, D, G, Z, g, z, bits24=True)
+    exact = orc.ltimes("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    scale = orc.ltimes_absscale("DGZ", len(g), 1, D, NM, L, cols).reshape(NM, -1)
+    errs = {}
+    for dt, bound in ((P.SJ_BF16, 2 * UB + UB * UB + gs(D + 1)), (P.SJ_BF16X3, 3 * UB * UB + gs(3 * D + 1))):
+        phi_d = run_bf16(P, dt, layout, Z, G, D, NM, dev(L), psi_d)
+        got = gather_columns(phi_d, layout, NM, G, Z, g, z).astype(np.float64)
+        errs[dt] = componentwise_err(got, exact, scale)
+        assert errs[dt] <= bound
+        del phi_d
+        torch.cuda.empty_cache()
+    print(f"{layout}: observed max componentwise error plain {errs[P.SJ_BF16]:.3e}, compensated {errs[P.SJ_BF16X3]:.3e}")
+    assert errs[P.SJ_BF16X3] < errs[P.SJ_BF16] / 50
+    del psi_d
+    torch.cuda.empty_cache()
 
 
 def test_bf16_large_config_sampled(P, orc):

@@ -15,8 +15,6 @@ def test_candidate_set_is_the_tuners():
         got = picker.candidates(s)
         want = []
         for lay in sj.LAYOUTS:
-            if s["dtype"] != sj.SJ_F64 and lay not in picker.COLUMN_LAYOUTS:
-                continue
             for c in tune.candidates(sj.SJ_LTIMES, lay, s["Z"], s["G"], s["D"], s["NM"], s["dtype"]):
                 try:
                     sj.sj_resolve(sj.SJ_LTIMES, **picker.spec_of(s, dict(layout=lay, **c)))
