@@ -432,7 +432,14 @@ def test_mass_specs(P):
     co = P.SJ_FLAG_COMPILE_ONLY
     base = dict(D=4, NM=6, inputs=3, count=1000, flags=co)
     h = P.sj_specialize(P.SJ_MASS, **base)
-    assert P.sj_handle_info(h)["kernel_name"] == "sj_mass_pa_3d_d4_q6"
+    # default: the pipelined form, four hexahedra per group, 64-thread workgroups
+    assert P.sj_handle_info(h)["kernel_name"] == "sj_mass_pa_pipe_3d_d4_q6"
+    r = P.sj_resolve(P.SJ_MASS, **base)
+    assert (r["order"], r["tile_n"], r["block"]) == (2, 4, 64)
+    h1 = P.sj_specialize(P.SJ_MASS, **dict(base, order=1))
+    assert P.sj_handle_info(h1)["kernel_name"] == "sj_mass_pa_3d_d4_q6"
+    # large elements: the staged form (the pipelined one would hold too many registers)
+    assert P.sj_resolve(P.SJ_MASS, **dict(base, D=12, NM=12))["order"] == 1
     src = P.sj_emit_source(P.SJ_MASS, **base)
     assert "#define SJ_DIM 3" in src and "#define SJ_D1D 4" in src and "#define SJ_Q1D 6" in src
     for bad, status in ((dict(inputs=4), P.SJ_ERR_INVALID_ARG), (dict(D=33), P.SJ_ERR_INVALID_ARG),
