@@ -331,9 +331,11 @@ sj_status sj_run_mlp_bwd_noalloc(sj_handle h, void *const *ptrs, int nptrs, void
 
 /* Time a specialization (the measurement primitive of the autotuner): `warmup`
  * untimed launches, then `reps` launches, each bracketed by HIP events on
- * `stream`.  When flush_bytes > 0 the caller's scratch buffer `flush` is
- * overwritten before every timed launch (outside the bracket) so the launch
- * does not find its operands in L2 or the 256 MB last-level cache.
+ * `stream`.  When flush_bytes > 0 the caller's scratch buffer `flush`
+ * (16-byte aligned, else SJ_ERR_ALIGN) is read in full before every timed
+ * launch (outside the bracket) so the launch does not find its operands in L2
+ * or the 256 MB last-level cache.  Reading, not writing: a written buffer
+ * would leave dirty lines whose write-back falls into the timed launch.
  * times_ms[reps] receives each launch's duration; the stream is synchronized
  * before returning.  Pointers as for sj_run. */
 sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int reps, void *flush,

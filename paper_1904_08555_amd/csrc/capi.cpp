@@ -669,6 +669,7 @@ sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int
     clear_error();
     if (!h || !times_ms || reps < 1 || warmup < 0) return fail(SJ_ERR_INVALID_ARG, "bad timing arguments");
     if (flush_bytes && !flush) return fail(SJ_ERR_INVALID_ARG, "flush_bytes > 0 needs a flush buffer");
+    if (flush_bytes && ((uintptr_t)flush & 15u)) return fail(SJ_ERR_ALIGN, "flush buffer not 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < warmup; ++i) {
         sj_status s = sj_run(h, ptrs, nptrs, stream);
@@ -682,8 +683,8 @@ sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int
     }
     sj_status out = SJ_OK;
     for (int i = 0; i < reps && out == SJ_OK; ++i) {
-        if (flush_bytes && hipMemsetAsync(flush, i & 0xff, flush_bytes, st) != hipSuccess) {
-            out = fail(SJ_ERR_HIP, "flush memset failed");
+        if (flush_bytes && launch_flush_read(flush, flush_bytes, st) != hipSuccess) {
+            out = fail(SJ_ERR_HIP, "flush read failed");
             break;
         }
         (void)hipEventRecord(e0, st);

@@ -281,6 +281,23 @@ generic_bgemm(const int *__restrict__ n, const long long *__restrict__ off, cons
     }
 }
 
+// Reads `bytes` of the buffer at p (16-byte pieces, grid-stride) so that earlier
+// contents of L2 and the last-level cache are evicted by clean lines; the only
+// store is conditional on a value the XOR of real data practically never
+// reaches, which keeps the loads.
+typedef unsigned int sj_u4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) flush_read(sj_u4 *p, size_t n16, size_t tail, const unsigned char *tail_p)
+{
+    sj_u4 acc = {0u, 0u, 0u, 0u};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+        acc ^= __builtin_nontemporal_load(p + i);
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (size_t i = 0; i < tail; ++i) acc.x ^= tail_p[i];
+    if (n16 > 0 && acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u && acc.z == 0xf39cc060u && acc.w == 0x5cedc834u)
+        p[0] = acc;
+}
+
 // Offsets of logical (a, g, z) for an (A, G, Z) array stored in `layout` order.
 void layout_strides(int layout, long long A, long long G, long long Z, long long *sa, long long *sg, long long *sz)
 {
@@ -295,6 +312,20 @@ void layout_strides(int layout, long long A, long long G, long long Z, long long
 }
 
 }  // namespace
+
+namespace sj {
+
+hipError_t launch_flush_read(void *buf, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    const size_t n16 = bytes / 16;
+    const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>((n16 + 255) / 256, 8192));
+    hipLaunchKernelGGL(flush_read, dim3(grid), dim3(256), 0, st, (sj_u4 *)buf, n16, bytes % 16,
+                       (const unsigned char *)buf + n16 * 16);
+    return hipGetLastError();
+}
+
+}  // namespace sj
 
 extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *const *ptrs, int nptrs, void *stream)
 {

@@ -405,7 +405,7 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             key.full_unroll = 1;
         } else {
             // BF16 matrix-core LTimes: column axis contiguous, a 32- or 128-column tile per wave; D
-            // innermost (GZD, ZGD), a 32-row tile per wave (tile_n 1; D % 4 == 0 for 16-byte rows).
+            // innermost (GZD, ZGD), a 16-row tile per wave (tile_n 1; D % 4 == 0 for 16-byte pieces).
             if (s->order != 0 && s->order != 1) return fail(SJ_ERR_INVALID_ARG, "this structure has no order 2");
             key.order = 1;
             key.block = s->block ? s->block : 256;
@@ -413,7 +413,7 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             if (key.I == 1) {
                 if (s->D % 4 != 0) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes with D innermost needs D % 4 == 0");
                 if (s->tile_n != 0 && s->tile_n != 1)
-                    return fail(SJ_ERR_INVALID_ARG, "BF16 LTimes with D innermost takes tile_n 1 (32 rows per wave)");
+                    return fail(SJ_ERR_INVALID_ARG, "BF16 LTimes with D innermost takes tile_n 1 (16 rows per wave)");
             }
             // tile_n = columns per lane: 1 (4-byte loads, 32 columns per wave) or 4 (16-byte loads,
             // 128 columns per wave as four interleaved MFMA tiles; needs the column extent % 4 == 0).
@@ -425,7 +425,9 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             // per lane and the kernel spills (measured 21.9 ms against 2.38 ms at block 256)
             if (cpl == 4 && key.block > 512) return fail(SJ_ERR_UNSUPPORTED, "BF16 tile_n 4 needs a block of at most 512 threads");
             key.tile_n = cpl;
-            const int64_t frag_bytes = ((s->NM + 31) / 32) * ((s->D + 15) / 16) * 64 * 16;
+            // L's hi (and lo) fragments: 32x16 tiles in the column forms, 16x32 in the row form
+            const int64_t frag_bytes = (key.I == 1 ? ((s->NM + 15) / 16) * ((s->D + 31) / 32)
+                                                   : ((s->NM + 31) / 32) * ((s->D + 15) / 16)) * 64 * 16;
             if (frag_bytes * (s->dtype == SJ_BF16X3 ? 2 : 1) > 160 * 1024)
                 return fail(SJ_ERR_UNSUPPORTED, "BF16 weight fragments exceed 160 KiB of LDS");
             if (s->D > 256) return fail(SJ_ERR_UNSUPPORTED, "BF16 LTimes keeps a column's D values in registers: D <= 256");
@@ -699,7 +701,7 @@ Geometry key_geometry(const SpecKey &k)
             g.grid = (unsigned)((k.B + rows_per_block - 1) / rows_per_block);
         } else if (k.variant == SJ_VAR_MFMA) {
             const int64_t cols = k.tile_n == 4 ? 128 : 32;
-            const int64_t tiles = k.I == 1 ? (k.B + 31) / 32 : k.B * ((k.I + cols - 1) / cols);
+            const int64_t tiles = k.I == 1 ? (k.B + 15) / 16 : k.B * ((k.I + cols - 1) / cols);
             const int64_t waves = k.block / 64;
             g.grid = (unsigned)std::min<int64_t>((tiles + waves - 1) / waves, 2048);
         }

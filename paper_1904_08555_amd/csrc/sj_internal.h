@@ -95,6 +95,10 @@ sj_status check_ptrs(void *const *ptrs, int nptrs, int expect, const size_t *byt
 sj_status launch_mlp_bwd(const sj_handle_ *h, void *th, void *X, void *t, void *g, void *loss, void *ws,
                          hipStream_t st);
 
+// Read `bytes` of `buf` on stream st (evicts L2 and the last-level cache with
+// clean lines; used between timed launches).
+hipError_t launch_flush_read(void *buf, size_t bytes, hipStream_t st);
+
 // Resolve and keep the device address of `device`'s copy of the static MLP
 // scratch array; `device` must be current.  Idempotent.
 sj_status noalloc_setup(int device);

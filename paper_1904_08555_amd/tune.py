@@ -33,7 +33,7 @@ per array in {1024, 2048, 4096}, 16x16 tiles per work item in {1, 2, 4},
 block in {512, 1024} and the next window prefetched or not; the wave form
 (each wave owns a window) with windows of {256, 512} elements, {1, 2} tiles
 per item, block 256  (<= 40).  Each candidate is timed on the caller's batch
-through a plan, with the caller's scratch buffer written before every timed
+through a plan, with the caller's scratch buffer read before every timed
 launch so that the batch is read from HBM.
 """
 from __future__ import annotations
@@ -62,8 +62,8 @@ def bgemm_candidates() -> list:
 def tune_bgemm(n_host, A, B, C, cands=None, reps: int = 5, warmup: int = 1, flush=None, farm=None):
     """Time every batched-product candidate on the caller's batch (sizes
     n_host, device arrays A, B, C as for sj_batch_run).  ``flush`` (a device
-    tensor) is overwritten before every timed launch.  Returns the same dict
-    as tune_exhaustive."""
+    tensor) is read in full before every timed launch, so the batch comes from
+    HBM.  Returns the same dict as tune_exhaustive."""
     import torch
     cands = bgemm_candidates() if cands is None else cands
     if farm is not None:
@@ -84,7 +84,7 @@ def tune_bgemm(n_host, A, B, C, cands=None, reps: int = 5, warmup: int = 1, flus
             ts = []
             for _ in range(reps):
                 if flush is not None:
-                    flush.fill_(1)
+                    flush.sum()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 sj.sj_batch_run(plan, A, B, C)
