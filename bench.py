@@ -47,49 +47,38 @@ LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 # were taken on: a kernel whose source has changed since reports traffic null.  The summaries with the
 # commands are the *_hbm_counters.md and bgemm_*_counters.md files under profiles/.
 MEASURED_TRAFFIC = {
-    # HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB (factors from a 1 GiB device copy),
-    # keyed by the SHA-1 of the emitted source the counters were taken on.
     # Z=32768 G=32 D=96 NM=16, the tuned specializations of the six nestings:
-    "a6f46348492bcdfd72c5cefed2cefafd23102547": 939814010,  # sj_ltimes_direct_dgz
-    "89c58e2ebb508b12336bcd6a790b761a37a875b2": 940363515,  # sj_lplustimes_cols_mfma_dgz
-    "b6d6da413a756dc954db8fcbf4f586e239342041": 939779834,  # sj_ltimes_direct_dzg
-    "2fce2b3e613e8628a020b669659b960ac7a3d9ba": 940332283,  # sj_lplustimes_cols_mfma_dzg
-    "858625ac709482476393c2c4337e7ac79257878f": 940025525,  # sj_ltimes_direct_gdz
-    "eabf1e426515efd23bb94fd27967cb38947ab96f": 940663867,  # sj_lplustimes_cols_mfma_gdz
-    "e2f4680432ca699cac6a3dd564cd98b9423f75ae": 939710460,  # sj_ltimes_rows_mfma_lds_gzd
-    "7d0562e5aabb0386599d1ba19780c26f9cab0b4d": 939746045,  # sj_lplustimes_rows_mfma_gzd
-    "f303a0f1a4664f56e737754a87e151907e3b93a9": 939772987,  # sj_ltimes_direct_zdg
-    "198e190815ed8b22063d73fb3f6a1ca016170b7d": 940265275,  # sj_lplustimes_cols_mfma_zdg
-    "385b9213b1c196f5763daab7b57762938b92611d": 939708156,  # sj_ltimes_rows_mfma_lds_zgd
-    "c524a2bbfc0f9a1e5e68eb37e59b080356775bee": 939764733,  # sj_lplustimes_rows_mfma_zgd
-    "456ff6bccbb93f1b5b963602531428289040ee2d": 940383099,  # sj_lplustimes_cols_mfma_zdg (unroll 2)
-    # other winners of the tuning on other boxes (LTimes DGZ tile 2 unroll 8, DZG tile 2 unroll 16
-    # block 512 order 2, LPlusTimes ZDG direct unroll 8 block 512)
-    "21b517bf80987334c6518ddecdb0091fd0dd45ce": 939787834,  # sj_ltimes_direct_dgz
-    "11ab1f5d02c74da13a3374820380f266957586a9": 939813114,  # sj_ltimes_direct_dzg
-    "dd8ff4aabde3ef06e5e21b8913d94f04cef11817": 940570423,  # sj_lplustimes_direct_zdg
-    # fused LTimes + LPlusTimes (phi written too), scattering (4 materials in zone regions),
-    # mass operator, BF16 LTimes: the default specializations of their workloads
-    "08de64ddce1c10477dfd9fb1f82c56008bd3d5f1": 1746069941,  # sj_ltimes_lplus_direct_dgz
-    "bfbba7d7caf51feaf1630a0d1c790da03062259b": 1746087286,  # sj_ltimes_lplus_direct_dzg
-    "17a60d0960937ba3962cf753e6e07200227dc6fe": 1746373814,  # sj_ltimes_lplus_direct_gdz
-    "cff7a5f6311098a7c3d8e1207d23517039285f75": 1746157747,  # sj_ltimes_lplus_rows_mfma_lds_gzd
-    "7974d54267365633a13564ed43b1ffa87ee583bc": 1746272694,  # sj_ltimes_lplus_direct_zdg
-    "e4d18d900fda6f5b2812b77a6162f628b58592c4": 1746151474,  # sj_ltimes_lplus_rows_mfma_lds_zgd
-    "db2131e0fc892566b4bc53ee6dafc54c66662b03": 1424929368,  # sj_mass_pa_3d_d4_q6
-    "93d86dd58ff927362edaf65b66937e50fd07b9e7": 1088023734,  # sj_mass_pa_2d_d4_q6
-    "793f46646f1f1acf9ffee52144a18fa02ea8f8f0": 12885965361,  # sj_ltimes_bf16w_dgz
-    "f36b06a45ca9a0861681d0b25d87fe584259e6d1": 12885542902,  # sj_ltimes_bf16x3w_dgz
-    "9dabc2ab7befcca15ec109b18caa3f63b1a1ff68": 12885410359,  # sj_ltimes_bf16_dgz
-    "de9ad205e63083d804b2eb26ab64574989d9ddc4": 12885481654,  # sj_ltimes_bf16x3_dgz
-    "e120e93ca86b864e241fff0aa89efe2e4319e291": 270830453,  # sj_scattering_direct_dgz
-    "4e2c3ac84a7f2b325fb8fc8e47541b8ee6cec3e7": 271573028,  # sj_scattering_direct_dzg
-    "52cb2358ddd2f1a46a9680477c17eef9ccfcaa09": 271022197,  # sj_scattering_direct_gdz
-    "4d2b73c740ba615ace95af5f2ede020de2505f14": 270267094,  # sj_scattering_direct_gzd
-    "312fabfc2ba62328ebd0a8aa49e65a69c7e91586": 271223274,  # sj_scattering_direct_zdg
-    "b1f109944946633eeb6ab6f0890ffd3612cebb81": 269936663,  # sj_scattering_direct_zgd
+    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 940032251,  # sj_lplustimes_cols_mfma_zdg
+    "caf4ba83110b0c9b595ccea83e82d168fa284f15": 940778229,  # sj_lplustimes_direct_dgz
+    "2a39f0c4aac61a118f1eadf2b4dde6fcb1b97a78": 940753013,  # sj_lplustimes_direct_dzg
+    "b2de5e78eac041dbf814c28dbcc56b849164c502": 940605045,  # sj_lplustimes_direct_gdz
+    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 939739133,  # sj_lplustimes_rows_mfma_gzd
+    "e92572674af57126b26f9a13a65126eeecfa5e3b": 939749117,  # sj_lplustimes_rows_mfma_zgd
+    "aac6be0336c61377439e3d3e3634416ed9e6bae9": 939996918,  # sj_ltimes_direct_dgz
+    "eab71f4174303315d32d91274d4ae3998ebd0aa5": 939996278,  # sj_ltimes_direct_dzg
+    "11390ff2859129b666d598b3a0cfb489186094d5": 939999222,  # sj_ltimes_direct_gdz
+    "293f2f0f3e5924e34ad9e0701bddaf5e21362f38": 939734779,  # sj_ltimes_direct_zdg
+    "b780dade1ba9509a8d304488318c03b07830cce1": 939694844,  # sj_ltimes_rows_mfma_lds_gzd
+    "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 939694844,  # sj_ltimes_rows_mfma_lds_zgd
+    # scattering (4 materials in zone regions, Z=32768 G=32 NM=16), default specializations:
+    "68bae0dcef15aa6a98d2d54c611f996f26be545a": 270875084,  # sj_scattering_direct_dgz
+    "7e1a3e6665d1330ed3855db7588689b8b416c008": 271485379,  # sj_scattering_direct_dzg
+    "e1fb7282b229e12092619af67a6872aaacac31a6": 270873931,  # sj_scattering_direct_gdz
+    "5b273898027180bb79c395b49cf8c70e35f9030d": 270032989,  # sj_scattering_direct_gzd
+    "1d1c67261e9bcacdc663123d9634d873395b25ab": 271244613,  # sj_scattering_direct_zdg
+    "f0a893edca371ae328b11107c4a596cd243f06c2": 270058716,  # sj_scattering_direct_zgd
+    # mass operator (hex 500k elements, quad 2M elements, D=4 Q=6), default specializations:
+    "760b6364988d89ff622be6ce3a7a360bcd546ea1": 1088244849,  # sj_mass_pa_pipe_2d_d4_q6
+    "4d3e1c1b6b941ce74290c31c71bad133adf2f5e3": 1376604732,  # sj_mass_pa_pipe_3d_d4_q6
+    # BF16 LTimes, Z=262144 G=64 D=128 NM=64 (psi and phi FP32):
+    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 12885323831,  # sj_ltimes_bf16_dgz
+    "32ebd620c1345acf1aacf5689aae83faa50f619a": 13790908334,  # sj_ltimes_bf16_rows_zgd
+    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 12885784689,  # sj_ltimes_bf16w_dgz
+    "064caca9d342bd247e528f7049d4fd9123058c51": 12885361654,  # sj_ltimes_bf16x3_dgz
+    "52d1df12cafaf9fec65f4f34596448a022ad7c32": 14907656065,  # sj_ltimes_bf16x3_rows_zgd
+    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 12885470774,  # sj_ltimes_bf16x3w_dgz
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
-    "2264ec0462c4d7fefb670793dce5411d5c810da1": 533950934,  # sj_bgemm_persistent
+    "2264ec0462c4d7fefb670793dce5411d5c810da1": 533994725,  # sj_bgemm_persistent
 }
 
 
@@ -838,15 +827,30 @@ def bench_small(a):
         gdev.fill(psi, 0, gen.ARR_PSI, gdev.DIST_U01, 0, (D, G, Z))
         sets.append((psi, torch.empty(NM * G * Z, dtype=torch.float64, device="cuda"),
                      torch.empty(D * G * Z, dtype=torch.float64, device="cuda")))
-    spec_l = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM)
-    spec_p = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM)
+    # the specializations come from the exhaustive tuner, timed on this shape with a 1 GiB read
+    # between launches (the launch's operands, 17 MB, would otherwise sit in the caches)
+    tuned = {}
+    if not a.no_tune:
+        from paper_1904_08555_amd import tune
+        flush = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+        for kname, kid, ptrs in (("ltimes", P.SJ_LTIMES, [L_d, sets[0][0], sets[0][1]]),
+                                 ("lplustimes", P.SJ_LPLUSTIMES, [Lp_d, sets[0][1], sets[0][2]])):
+            r = tune.tune_exhaustive(kid, "DGZ", Z, G, D, NM, ptrs, reps=10, warmup=2, flush=flush, threads=8)
+            tuned[kname] = r["best"]
+        del flush
+    spec_l = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM, **tuned.get("ltimes", {}))
+    spec_p = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM, **tuned.get("lplustimes", {}))
     h_l = P.sj_specialize(P.SJ_LTIMES, spec_l)
     h_p = P.sj_specialize(P.SJ_LPLUSTIMES, spec_p)
     nbytes = algorithmic_bytes(Z, G, D, NM)
     res = {}
     for name, h, kid, spec, ptrs in (
             ("ltimes", h_l, P.SJ_LTIMES, spec_l, [[L_d, s[0], s[1]] for s in sets]),
-            ("lplustimes", h_p, P.SJ_LPLUSTIMES, spec_p, [[Lp_d, s[1], s[2]] for s in sets])):
+            ("lplustimes", h_p, P.SJ_LPLUSTIMES, spec_p, [[Lp_d, s[1], s[2]] for s in sets]),
+            ("ltimes_default", P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM), P.SJ_LTIMES,
+             P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM), [[L_d, s[0], s[1]] for s in sets]),
+            ("lplustimes_default", P.sj_specialize(P.SJ_LPLUSTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM),
+             P.SJ_LPLUSTIMES, P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM), [[Lp_d, s[1], s[2]] for s in sets])):
         for p in ptrs:                                   # warm up, outside capture
             P.sj_run(h, p)
         torch.cuda.synchronize()
@@ -895,7 +899,9 @@ def bench_small(a):
         "warmup": 3, "ms_per_step": round(tot * 1e-3, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (SplitMix64 counter generator, seed 0)",
         "config": {"workload": f"LTimes+LPlusTimes, DGZ, FP64, Z={Z} G={G} D={D} NM={NM}",
-                   "buffer_sets": nset, "launches_per_graph": nset},
+                   "buffer_sets": nset, "launches_per_graph": nset,
+                   "specialization": "exhaustive tuner" if tuned else "library defaults"},
+        "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": res["ltimes"]["graph_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res["ltimes"]["graph_frac"], "traffic": None, "kernel": res["ltimes"]["kernel"],
                      "avg_us": res["ltimes"]["graph_us_per_launch"], "bytes_per_launch": nbytes},

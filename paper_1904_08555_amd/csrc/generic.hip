@@ -187,6 +187,95 @@ generic_rows(const double *__restrict__ W, const double *__restrict__ in, double
     }
 }
 
+// The same row contraction on the FP64 matrix cores with run-time sizes:
+// v_mfma_f64_16x16x4f64 (A lane l holds A[l%16][l/16], B lane l holds
+// B[l/16][l%16], C register i of lane l holds C[4i + l/16][l%16]).  A wave
+// takes 16-row tiles grid-stride: the tile's rows arrive as one contiguous run
+// into a per-wave LDS tile (row pitch red + 1), and for every 16-output block a
+// run-time loop over 4-deep reduction steps feeds the MFMAs with A = the rows
+// and B = W (staged in LDS once per workgroup), two accumulators in turn; each
+// block's outputs are stored from the C registers (sixteen lanes write sixteen
+// consecutive outputs of a row).
+constexpr int kRowWaves = 4;
+
+__global__ void __launch_bounds__(kRowWaves * 64)
+generic_rows_mfma(const double *__restrict__ W, const double *__restrict__ in, double *__restrict__ out, long long N,
+                  int red, int outn)
+{
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    extern __shared__ double lds[];
+    const int pitch = red + 1;
+    double *wl = lds;                                                  // [outn][red]
+    double *tile = lds + (long long)outn * red + (threadIdx.x >> 6) * (16 * pitch);
+    const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
+    for (int e = threadIdx.x; e < outn * red; e += kRowWaves * 64) wl[e] = W[e];
+    __syncthreads();
+    const long long tiles = (N + 15) / 16;
+    for (long long t = (long long)blockIdx.x * kRowWaves + (threadIdx.x >> 6); t < tiles;
+         t += (long long)gridDim.x * kRowWaves) {
+        const long long r0 = t * 16;
+        const int rows = (int)(N - r0 < 16 ? N - r0 : 16);
+        const int nin = rows * red;
+        const double *src = in + r0 * red;
+        {   // eight loads in flight per lane before their LDS writes
+            constexpr int U = 8;
+            int r = lane / red, c = lane % red;
+            const int dr = 64 / red, dc = 64 % red;
+            for (int e0 = lane; e0 < nin; e0 += U * 64) {
+                double v[U];
+                int at[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * 64;
+                    at[u] = r * pitch + c;
+                    v[u] = e < nin ? src[e] : 0.0;
+                    r += dr;
+                    c += dc;
+                    if (c >= red) { c -= red; ++r; }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (e0 + u * 64 < nin) tile[at[u]] = v[u];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // rows past the tile's end read row 0 (their results are not stored)
+        const double *arow = tile + (m < rows ? m : 0) * pitch;
+        const int nob = (outn + 15) / 16, nkb = (red + 3) / 4;
+        double *dst = out + r0 * outn;
+        for (int ob = 0; ob < nob; ++ob) {
+            const int o = ob * 16 + m;
+            const double *wrow = wl + (long long)(o < outn ? o : 0) * red;
+            d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            int kb = 0;
+            for (; kb + 1 < nkb; kb += 2) {
+                const int k0 = 4 * kb + q, k1 = k0 + 4;
+                const double a0 = k0 < red ? arow[k0] : 0.0, a1 = k1 < red ? arow[k1] : 0.0;
+                const double b0 = (o < outn && k0 < red) ? wrow[k0] : 0.0;
+                const double b1 = (o < outn && k1 < red) ? wrow[k1] : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+            }
+            if (kb < nkb) {
+                const int k0 = 4 * kb + q;
+                const double a0 = k0 < red ? arow[k0] : 0.0;
+                const double b0 = (o < outn && k0 < red) ? wrow[k0] : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+            }
+            // C register i of lane l: row 4i + l/16, output o; sixteen lanes write 16 consecutive
+            // outputs of one row
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * i + q < rows && o < outn) dst[(long long)(4 * i + q) * outn + o] = acc0[i] + acc1[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");   // A reads done before the next tile's run
+    }
+}
+
 // Rows per workgroup of generic_rows: the row tiles (and W, when it is staged)
 // within 64 KiB of LDS.
 inline int generic_rows_tile(long long red, long long outn, bool wlds)
@@ -360,6 +449,18 @@ extern "C" sj_status sj_generic_run(sj_kernel k, const sj_spec *spec, void *cons
         const double *L = (const double *)ptrs[0];
         const double *in = (const double *)ptrs[1];
         double *outp = (double *)ptrs[2];
+        if (st_.ad == 1 && st_.bd == 1 && A_in * A_out + 64 * (A_in + 1) <= 8192) {
+            // the reduction axis is innermost in both arrays, W and four 16-row tiles fit in 64 KiB
+            // of LDS: the matrix-core row kernel with run-time sizes
+            const long long tiles = ((long long)cols + 15) / 16;
+            const unsigned grid = (unsigned)std::min<long long>((tiles + kRowWaves - 1) / kRowWaves, 8192);
+            const size_t shm = ((size_t)(A_in * A_out) + 64 * (size_t)(A_in + 1)) * 8;
+            hipLaunchKernelGGL(generic_rows_mfma, dim3(grid), dim3(kRowWaves * 64), shm, st, L, in, outp,
+                               (long long)cols, (int)A_in, (int)A_out);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(SJ_ERR_LAUNCH, std::string("generic launch: ") + hipGetErrorString(e));
+            return SJ_OK;
+        }
         if (st_.ad == 1 && st_.bd == 1 && A_in + A_out + 2 <= 8192) {
             // the reduction axis is innermost in both arrays: rows staged through LDS (serves the
             // generic call and the per-nesting one alike: the access pattern is the nesting's); W

@@ -188,8 +188,8 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
     if ((s->flags & SJ_FLAG_XCD_CONTIGUOUS) && (s->flags & SJ_FLAG_XCD_INTERLEAVED))
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_XCD_CONTIGUOUS and SJ_FLAG_XCD_INTERLEAVED exclude each other");
     if ((s->flags & (SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED)) && k != SJ_LTIMES && k != SJ_LPLUSTIMES &&
-        k != SJ_LTIMES_LPLUS)
-        return fail(SJ_ERR_INVALID_ARG, "the XCD flags apply to LTimes, LPlusTimes and the fused kernel");
+        k != SJ_LTIMES_LPLUS && k != SJ_SCATTERING)
+        return fail(SJ_ERR_INVALID_ARG, "the XCD flags apply to LTimes, LPlusTimes, the fused kernel and scattering");
     if ((s->flags & SJ_FLAG_ACCUMULATE) && k != SJ_LTIMES && k != SJ_LPLUSTIMES)
         return fail(SJ_ERR_INVALID_ARG, "SJ_FLAG_ACCUMULATE applies to LTimes and LPlusTimes");
     if (k == SJ_LTIMES_LPLUS) {
@@ -567,6 +567,10 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
         key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
         key.order = zdg_nm ? 2 : 1;
+        // workgroup order over the XCDs: explicit flag, else the hardware's round-robin order
+        const bool xcd = (s->flags & SJ_FLAG_XCD_CONTIGUOUS) != 0;
+        key.flags &= ~(SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
+        key.flags |= xcd ? SJ_FLAG_XCD_CONTIGUOUS : SJ_FLAG_XCD_INTERLEAVED;
         return (*out = key), SJ_OK;
     }
     if (k == SJ_MLP_FWD || k == SJ_MLP_BWD || k == SJ_ADAM) {
@@ -888,7 +892,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
           << "\n#define SJ_SZ " << sz << sfx << "\n#define SJ_LANE_NM " << (lane_nm ? 1 : 0) << "\n#define SJ_RUN_LINES "
           << ((sg == 1 && std::min(snm, sz) == G) ? 1 : 0) << "\n#define SJ_SLDS "
           << ((lane_nm && nl * (G * G + 2) * 8 <= 64 * 1024) ? 1 : 0) << "\n#define SJ_BLOCK "
-          << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n";
+          << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n"
+          << "#define SJ_XCD " << ((k.flags & SJ_FLAG_XCD_CONTIGUOUS) ? 8 : 0) << "\n" << kXcdHelper;
         body = kTpl_scattering_direct;
         static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
         *name = std::string("sj_scattering_direct_") + lay[k.layout];
