@@ -82,6 +82,37 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Matrix-core busy fraction measured with rocprofv3 (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE / 8
+# x 1024 SIMDs), keyed like MEASURED_TRAFFIC; the summary with the commands is
+# profiles/mfma_busy_moments_bf16_bgemm_counters.md.
+MEASURED_MFMA_BUSY = {
+    # Z=32768 G=32 D=96 NM=16 (FP64 matrix cores)
+    "b780dade1ba9509a8d304488318c03b07830cce1": 0.258,  # sj_ltimes_rows_mfma_lds_gzd
+    "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 0.260,  # sj_ltimes_rows_mfma_lds_zgd
+    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 0.185,  # sj_lplustimes_rows_mfma_gzd
+    "e92572674af57126b26f9a13a65126eeecfa5e3b": 0.182,  # sj_lplustimes_rows_mfma_zgd
+    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 0.226,  # sj_lplustimes_cols_mfma_zdg
+    # Z=262144 G=64 D=128 NM=64: FP64 column kernel, BF16 forms
+    "60467b2e08b71a9f23cd2cf2872db0e82932347b": 0.774,  # sj_ltimes_cols_mfma_dgz
+    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 0.039,  # sj_ltimes_bf16_dgz
+    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 0.053,  # sj_ltimes_bf16w_dgz
+    "32ebd620c1345acf1aacf5689aae83faa50f619a": 0.046,  # sj_ltimes_bf16_rows_zgd
+    "064caca9d342bd247e528f7049d4fd9123058c51": 0.139,  # sj_ltimes_bf16x3_dgz
+    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 0.182,  # sj_ltimes_bf16x3w_dgz
+    "52d1df12cafaf9fec65f4f34596448a022ad7c32": 0.156,  # sj_ltimes_bf16x3_rows_zgd
+    # batched products, 200,000 instances n ~ U{3..16}
+    "2264ec0462c4d7fefb670793dce5411d5c810da1": 0.170,  # sj_bgemm_persistent
+}
+
+
+def mfma_evidence(P, kernel, spec, flops, us, peak_tflops):
+    """Matrix-core use of a launch: the counter-measured busy fraction (None when the counters were
+    not taken on this exact kernel source) and the algorithmic flop rate against the dtype's peak."""
+    tf = flops / (us * 1e-6) / 1e12
+    return {"busy_frac": MEASURED_MFMA_BUSY.get(source_sha1(P, kernel, spec)),
+            "achieved_tflops": round(tf, 2), "peak_tflops": peak_tflops, "frac_of_peak": round(tf / peak_tflops, 4)}
+
+
 def source_sha1(P, kernel, spec):
     """SHA-1 of the emitted source of a specialization: names the exact kernel that counters were taken on."""
     import hashlib
@@ -119,6 +150,9 @@ def parse():
     ap.add_argument("--tuned-json", default="",
                     help="moments: take the tuned specializations from this file (written by an earlier run to "
                          "<out-dir>/tuned_moments.json) instead of tuning")
+    ap.add_argument("--in-step-sweep", default="",
+                    help="moments: comma-separated NESTING:kernel items (e.g. GZD:ltimes); every tuner candidate of "
+                         "each, with ordinary and with nontemporal stores, is timed inside the whole step")
     ap.add_argument("--picker-part", default="all", choices=("all", "collect", "evaluate"))
     ap.add_argument("--picker-slice", default="", help="held-out shapes lo:hi for --picker-part collect")
     ap.add_argument("--picker-data", default="", help="comma-separated collect outputs for --picker-part evaluate")
@@ -266,10 +300,10 @@ def bench_moments(a):
             rc = lib.sj_specialize(kid, ctypes.byref(s), ctypes.byref(hout))   # cache lookup (hit)
             if rc != 0:
                 raise RuntimeError(P.sj_last_error())
-            if events is not None:
+            if events is not None and key in events:
                 events[key][0].record(stream)
             rc = lib.sj_run(hout, arrs[key], 3, sptr)
-            if events is not None:
+            if events is not None and key in events:
                 events[key][1].record(stream)
             if rc != 0:
                 raise RuntimeError(P.sj_last_error())
@@ -322,6 +356,42 @@ def bench_moments(a):
         with open(os.path.join(ROOT, a.out_dir, "tuned_moments.json"), "w") as f:
             json.dump({f"{k[1]}_{k[0]}": v for k, v in tuned.items()}, f)
 
+    # Optional: every candidate of the named kernels inside the whole step (the other kernels at
+    # their chosen specializations): the kernel's own median time and the step's
+    sweep = {}
+    if a.in_step_sweep:
+        from paper_1904_08555_amd import tune
+        for item in a.in_step_sweep.split(","):
+            lay, kname = item.split(":")
+            key = (lay, kname)
+            kid, keep = specs[key][0], specs[key]
+            stores = (P.SJ_FLAG_STORES_CACHED, P.SJ_FLAG_STORES_NONTEMPORAL)
+            cands = [dict(c, flags=(c.get("flags", 0) | fl)) for c in tune.candidates(kid, lay, Z, G, D, NM)
+                     for fl in stores]
+            base = dict(layout=lay, Z=Z, G=G, D=D, NM=NM)
+            rows = []
+            for c, h, err in tune.compile_all(kid, base, tune.distinct(kid, base, cands)):
+                if h is None:
+                    continue
+                specs[key] = (kid, P.make_spec(**base, **c))
+                for _ in range(2):
+                    step()
+                kev, sev = [], []
+                for _ in range(9):
+                    e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    s0.record(stream)
+                    step({key: e})
+                    s1.record(stream)
+                    kev.append(e)
+                    sev.append((s0, s1))
+                torch.cuda.synchronize()
+                rows.append(dict(spec=c, kernel=P.sj_handle_info(h)["kernel_name"],
+                                 kernel_us=round(statistics.median(x.elapsed_time(y) for x, y in kev) * 1e3, 1),
+                                 step_us=round(statistics.median(x.elapsed_time(y) for x, y in sev) * 1e3, 1)))
+            specs[key] = keep
+            sweep[item] = sorted(rows, key=lambda r: r["step_us"])
+
     # the specializations the timed steps use (after any refinement)
     for key in order:
         kid, s = specs[key]
@@ -330,7 +400,8 @@ def bench_moments(a):
                                          tile_k=info["tile_k"], unroll=info["unroll"], block=info["block"],
                                          vgprs=info["vgprs"], scratch=info["scratch_bytes"],
                                          occupancy=info["occupancy"], lds=info["lds_bytes"],
-                                         src_sha1=source_sha1(P, kid, s), traffic=measured_traffic(P, kid, s))
+                                         src_sha1=source_sha1(P, kid, s), traffic=measured_traffic(P, kid, s),
+                                         mfma_busy=MEASURED_MFMA_BUSY.get(source_sha1(P, kid, s)))
     # cold specialization cost: ten keys never compiled before, in this process
     cold = []
     for i in range(10):
@@ -499,7 +570,8 @@ def bench_moments(a):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, *specs[dom]),
                      "kernel": f"{dom[1]}_{dom[0]}", "avg_us": round(dom_ms * 1e3, 2),
                      "bytes_per_launch": nbytes, "measured_copy_gbs": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4),
+                     "mfma": mfma_evidence(P, *specs[dom], 2 * D * NM * G * Z, dom_ms * 1e3, 78.6)},
         "step_frac_of_measured_copy": round(value / copy_gbs, 4),
         "value_note": ("effective rate of the step: algorithmic bytes / step time; LPlusTimes may read part of phi "
                        "from the last-level cache right after LTimes writes it, so per-kernel in-step figures of "
@@ -515,6 +587,7 @@ def bench_moments(a):
         "tuned": {f"{k[1]}_{k[0]}": v for k, v in tuned.items()},
         "tune_s": None if tune_s is None else round(tune_s, 1),
         "refined_in_step": refined,
+        "in_step_sweep": sweep or None,
         "value_default_specializations": None if default_value is None else round(default_value, 1),
     }
     print(json.dumps(line), flush=True)
@@ -636,7 +709,8 @@ def bench_batched(a):
                      "unit": "GB/s", "frac": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(P, P.SJ_BGEMM, P.make_spec(**tile)),
                      "kernel": info["kernel_name"], "avg_us": round(mean * 1e3, 2), "bytes_per_launch": nbytes,
-                     "src_sha1": source_sha1(P, P.SJ_BGEMM, P.make_spec(**tile))},
+                     "src_sha1": source_sha1(P, P.SJ_BGEMM, P.make_spec(**tile)),
+                     "mfma": mfma_evidence(P, P.SJ_BGEMM, P.make_spec(**tile), flops, mean * 1e3, 78.6)},
         "graph_us_median": round(med * 1e3, 2), "direct_launch_us_median": round(statistics.median(run_per) * 1e3, 2),
         "host_wall_ms_per_step_with_scratch_write": round(t_total * 1e3 / a.steps, 4),
         "generic_us": round(gmed * 1e3, 2),
@@ -680,7 +754,9 @@ def bench_bf16(a):
         res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
                          frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
                          vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"],
-                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec))
+                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec),
+                         mfma=mfma_evidence(P, P.SJ_LTIMES, spec, (3 if dt == P.SJ_BF16X3 else 1) * 2 * D * NM * G * Z,
+                                            ms * 1e3, 2500.0))
     # D innermost (ZGD): the row form, on the same logical values stored in that nesting
     gdev.fill(psi32, 0, gen.ARR_PSI, gdev.DIST_U01_24, LAYOUTS.index("ZGD"), (D, G, Z))
     for name, dt in (("bf16_zgd", P.SJ_BF16), ("bf16x3_zgd", P.SJ_BF16X3)):
@@ -692,7 +768,9 @@ def bench_bf16(a):
         res[name] = dict(ms=round(ms, 4), gbs=round(b32 / (ms * 1e-3) / 1e9, 1),
                          frac=round(b32 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernel=info["kernel_name"],
                          vgprs=info["vgprs"], agprs=info["agprs"], occupancy=info["occupancy"],
-                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec))
+                         src_sha1=source_sha1(P, P.SJ_LTIMES, spec), traffic=measured_traffic(P, P.SJ_LTIMES, spec),
+                         mfma=mfma_evidence(P, P.SJ_LTIMES, spec, (3 if dt == P.SJ_BF16X3 else 1) * 2 * D * NM * G * Z,
+                                            ms * 1e3, 2500.0))
     gdev.fill(psi32, 0, gen.ARR_PSI, gdev.DIST_U01_24, 0, (D, G, Z))
     del phi32
     psi64 = psi32.to(torch.float64)
@@ -702,13 +780,15 @@ def bench_bf16(a):
     flops = 2 * D * NM * G * Z
     # FP64: vector FMAs (DIRECT) and the FP64 matrix-core column kernel
     for name, var in (("f64", P.SJ_VAR_DIRECT), ("f64_mfma", P.SJ_VAR_MFMA)):
-        h = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=Z, G=G, D=D, NM=NM, variant=var)
+        spec = P.make_spec(layout="DGZ", Z=Z, G=G, D=D, NM=NM, variant=var)
+        h = P.sj_specialize(P.SJ_LTIMES, spec)
         t = P.sj_time_run(h, [L_d, psi64, phi64], warmup=a.warmup, reps=a.steps)
         ms = statistics.median(t)
         info = P.sj_handle_info(h)
         res[name] = dict(ms=round(ms, 4), gbs=round(b64 / (ms * 1e-3) / 1e9, 1), kernel=info["kernel_name"],
                          tflops=round(flops / (ms * 1e-3) / 1e12, 2),
-                         frac_fp64_peak=round(flops / (ms * 1e-3) / 78.6e12, 4))
+                         frac_fp64_peak=round(flops / (ms * 1e-3) / 78.6e12, 4),
+                         mfma=mfma_evidence(P, P.SJ_LTIMES, spec, flops, ms * 1e3, 78.6))
     best = res["bf16x3"]
     line = {
         "metric": "LTimes BF16 (split-compensated) GB/s at Z=262144 G=64 D=128 NM=64",
@@ -717,7 +797,8 @@ def bench_bf16(a):
         "dtype": "bf16x3 (fp32 accumulate)", "data": "synthetic (SplitMix64, seed 0)",
         "config": {"workload": "LTimes DGZ Z=262144 G=64 D=128 NM=64, psi FP32 in, phi FP32 out"},
         "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": best["frac"], "traffic": best["traffic"], "kernel": best["kernel"], "bytes_per_launch": b32},
+                     "frac": best["frac"], "traffic": best["traffic"], "kernel": best["kernel"], "bytes_per_launch": b32,
+                     "mfma": best["mfma"]},
         "modes": res,
     }
     print(json.dumps(line), flush=True)
@@ -951,15 +1032,18 @@ def bench_scattering(a):
         res[lay] = dict(us=round(t * 1e3, 1), gbs=round(nbytes / (t * 1e-3) / 1e9, 1),
                         frac=round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                         random_materials_us=round(tr * 1e3, 1), kernel=info["kernel_name"], vgprs=info["vgprs"],
+                        tile_n=info["tile_n"], block=info["block"], order=info.get("order"),
                         compile_ms=round(info["compile_ms"], 1), src_sha1=source_sha1(P, P.SJ_SCATTERING, spec),
                         traffic=measured_traffic(P, P.SJ_SCATTERING, spec))
-        if lay == "ZDG":   # the other thread order of this nesting (order 2: threads along nm)
-            h2 = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat, order=2))
-            t2, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_reg, phi, out]), a.steps, stream, flush)
-            t2r, _ = time_launches(lambda: P.sj_run(h2, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream,
+        if info["variant"] != P.SJ_VAR_DIRECT:   # the vector-FMA structure of this nesting beside it
+            hd = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat,
+                                                              variant=P.SJ_VAR_DIRECT))
+            td, _ = time_launches(lambda: P.sj_run(hd, [S_d, mat_reg, phi, out]), a.steps, stream, flush, warmup=10)
+            tdr, _ = time_launches(lambda: P.sj_run(hd, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream,
                                    flush)
-            res[lay]["threads_along_nm_us"] = round(t2 * 1e3, 1)
-            res[lay]["threads_along_nm_random_materials_us"] = round(t2r * 1e3, 1)
+            res[lay].update(direct_us=round(td * 1e3, 1), direct_random_materials_us=round(tdr * 1e3, 1),
+                            direct_kernel=P.sj_handle_info(hd)["kernel_name"],
+                            speedup_vs_direct=round(td / t, 3))
     dom = max(res, key=lambda k: res[k]["us"])
     line = {
         "metric": "scattering source GB/s over six nestings (specialized kernels)",

@@ -512,10 +512,10 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (s->count < 1 || s->count > 65536) return fail(SJ_ERR_INVALID_ARG, "count (materials) must be in [1, 65536]");
         if (s->NM > 4096) return fail(SJ_ERR_UNSUPPORTED, "NM is limited to 4096");
         if (s->G > 64) return fail(SJ_ERR_UNSUPPORTED, "scattering keeps a line's G values in registers: G <= 64");
-        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT)
-            return fail(SJ_ERR_UNSUPPORTED, "scattering has the DIRECT structure only");
-        if (s->tile_n != 0 || s->tile_k != 0 || s->unroll != 0 || s->order < 0 || s->order > 2)
-            return fail(SJ_ERR_INVALID_ARG, "scattering takes no tiles; order 0, 1 or 2");
+        if (s->variant != SJ_VAR_AUTO && s->variant != SJ_VAR_DIRECT && s->variant != SJ_VAR_MFMA)
+            return fail(SJ_ERR_UNSUPPORTED, "scattering has the DIRECT and MFMA structures");
+        if (s->tile_k != 0 || s->unroll != 0 || s->order < 0 || s->order > 2)
+            return fail(SJ_ERR_INVALID_ARG, "scattering takes tile_n (MFMA only) and order 0, 1 or 2");
         if (s->flags & SJ_FLAG_ACCUMULATE) return fail(SJ_ERR_INVALID_ARG, "scattering overwrites its output");
         const int64_t lines = s->NM * s->Z;
         if (lines > (int64_t(1) << 40) || s->G * lines > (int64_t(1) << 50)) return fail(SJ_ERR_INVALID_ARG, "array size overflows");
@@ -539,6 +539,43 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         case SJ_ZDG: sz = NMv * Gv; snm = Gv; sg = 1; break;
         default: sz = Gv * NMv; sg = NMv; snm = 1; break;
         }
+        // the default structure: the FP64 matrix cores wherever g or z is innermost and G <= 32
+        // (measured on MI355X at Z=32768 G=32 NM=16, four materials in zone regions, each launch
+        // after a 1 GiB read that empties the last-level cache: DZG 60.4 us against 135-138 us,
+        // ZDG 59.4 us against 148 us, DGZ 64.2 us against 76 us, GDZ 72.5 us against 80 us;
+        // materials drawn per zone 142-252 us against 340-358 us)
+        const bool mfma = (s->variant == SJ_VAR_MFMA) ||
+                          (s->variant == SJ_VAR_AUTO && (sg == 1 || sz == 1) && Gv <= 32);
+        if (mfma) {
+            // FP64 matrix cores: tiles of one moment and 16 zones, tile_n tiles per group of loads,
+            // persistent waves, the fragments of a matrix in registers; g innermost: the tile's
+            // lines through LDS rows; z innermost: lanes along z, no LDS
+            if (sg != 1 && sz != 1)
+                return fail(SJ_ERR_UNSUPPORTED, "the scattering MFMA structure needs g or z innermost (DZG, ZDG, DGZ, GDZ)");
+            if (Gv > 32) return fail(SJ_ERR_UNSUPPORTED, "the scattering MFMA structure holds G <= 32");
+            // order 1: moments outer (tiles in flight together run along z); order 2: zone blocks
+            // outer (tiles in flight together take the moments of the same zones); default: the
+            // nesting's outer axis first
+            key.order = s->order ? s->order : (sz > snm ? 2 : 1);
+            // defaults measured as above: one tile per group with zone blocks outer (ZDG), else two;
+            // 512-thread workgroups for the column form (DGZ 64.2 us against 65.0 at 256, GDZ 72.5
+            // against 75.9), 128 with zone blocks outer (ZDG 59.4 against 60.5), else 256
+            const int rt = s->tile_n ? s->tile_n : (key.order == 2 ? 1 : 2);
+            if (rt != 1 && rt != 2 && rt != 4) return fail(SJ_ERR_INVALID_ARG, "MFMA tile_n (tiles per group) must be 1, 2 or 4");
+            key.variant = SJ_VAR_MFMA;
+            key.tile_n = rt;
+            key.block = s->block ? s->block : (sg != 1) ? 512 : (key.order == 2) ? 128 : 256;
+            if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+            const int64_t tp = 16 * ((Gv + 15) / 16) + 2;   // LDS rows where g is innermost
+            if (sg == 1 && (int64_t)(key.block / 64) * rt * 16 * tp * 8 + 512 > 160 * 1024)
+                return fail(SJ_ERR_UNSUPPORTED, "scattering MFMA tiles exceed 160 KiB of LDS at this block size");
+            key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+            const bool xcd = (s->flags & SJ_FLAG_XCD_CONTIGUOUS) != 0;
+            key.flags &= ~(SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
+            key.flags |= xcd ? SJ_FLAG_XCD_CONTIGUOUS : SJ_FLAG_XCD_INTERLEAVED;
+            return (*out = key), SJ_OK;
+        }
+        if (s->tile_n != 0) return fail(SJ_ERR_INVALID_ARG, "tile_n is the MFMA structure's tiles per group");
         const bool run_lines = (sg == 1 && std::min(snm, sz) == Gv);
         // lanes along nm only where nm is the faster axis and g is not innermost, or on request
         // (order 2) in ZDG; measured on MI355X at Z=32768 G=32 NM=16 with four materials in zone
@@ -625,9 +662,10 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (lds > 160 * 1024) return fail(SJ_ERR_INVALID_ARG, "BGEMM window and block exceed 160 KiB of LDS");
         if (s->tile_k != 0) return fail(SJ_ERR_INVALID_ARG, "BGEMM takes no tile_k");
         // order (workgroup form): 1 = the next window is loaded after the current one is written
-        // back, 2 = its loads are issued before the current window's products (prefetch)
+        // back; d + 1 (d = 1..3) = the loads of the next d windows are in flight in registers,
+        // issued before the current window's products (prefetch depth d)
         const int order = s->order ? s->order : (wave_form ? 1 : 2);
-        if (order != 1 && order != 2) return fail(SJ_ERR_INVALID_ARG, "BGEMM order must be 0, 1 or 2");
+        if (order < 1 || order > 4) return fail(SJ_ERR_INVALID_ARG, "BGEMM order must be 0 .. 4");
         if (wave_form && order != 1) return fail(SJ_ERR_INVALID_ARG, "the BGEMM wave form has no prefetch order");
         key.order = order;
         return (*out = key), SJ_OK;
@@ -661,7 +699,11 @@ Geometry key_geometry(const SpecKey &k)
     Geometry g{0, (unsigned)k.block, 0};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
-    if (k.kernel == SJ_SCATTERING) {
+    if (k.kernel == SJ_SCATTERING && k.variant == SJ_VAR_MFMA) {
+        const int64_t groups = (k.NM * ((k.Z + 15) / 16) + k.tile_n - 1) / k.tile_n, waves = k.block / 64;
+        g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
+        g.persistent = 1;
+    } else if (k.kernel == SJ_SCATTERING) {
         g.grid = (unsigned)((k.NM * k.Z + k.block - 1) / k.block);
         if (scattering_pairs(k)) g.grid = (unsigned)((k.NM * ((k.Z + 1) / 2) + k.block - 1) / k.block);
         if (scattering_persistent(k)) {
@@ -882,6 +924,21 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         while ((nl + 1) * (nl + 1) <= NM - 1) ++nl;
         nl += 1;
         const bool lane_nm = (snm < sz) && (sg != 1 || k.order == 2);   // as in the key
+        static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
+        if (k.variant == SJ_VAR_MFMA) {
+            int ntl = 1, nts = 1;
+            if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
+            if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
+            o << "#define SJ_NM " << NM << "\n#define SJ_G " << G << "\n#define SJ_Z " << Z << sfx << "\n#define SJ_NMAT "
+              << k.rows << "\n#define SJ_NL " << nl << "\n#define SJ_SNM " << snm << sfx << "\n#define SJ_SZ " << sz << sfx
+              << "\n#define SJ_SG " << sg << sfx << "\n#define SJ_RT " << k.tile_n << "\n#define SJ_ZMAJOR " << (k.order == 2 ? 1 : 0)
+              << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD " << ntl
+              << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n"
+              << "#define SJ_XCD " << ((k.flags & SJ_FLAG_XCD_CONTIGUOUS) ? 8 : 0) << "\n" << kXcdHelper;
+            body = (sg == 1) ? kTpl_scattering_mfma_rows : kTpl_scattering_mfma_cols;
+            *name = std::string("sj_scattering_mfma_") + lay[k.layout];
+            o << "#define SJ_KERNEL_NAME " << *name << "\n";
+        } else {
         o << "#define SJ_PERSIST " << (scattering_persistent(k) ? 1 : 0) << "\n#define SJ_PAIR "
           << (scattering_pairs(k) ? 1 : 0) << "\n";
         int ntl = 1, nts = 1;   // phi is read once and phi_out written once: streamed
@@ -895,9 +952,9 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
           << k.block << "\n#define SJ_NT_LOAD " << ntl << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n"
           << "#define SJ_XCD " << ((k.flags & SJ_FLAG_XCD_CONTIGUOUS) ? 8 : 0) << "\n" << kXcdHelper;
         body = kTpl_scattering_direct;
-        static const char *lay[6] = {"dgz", "dzg", "gdz", "gzd", "zdg", "zgd"};
         *name = std::string("sj_scattering_direct_") + lay[k.layout];
         o << "#define SJ_KERNEL_NAME " << *name << "\n";
+        }
     }
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM) {
         o << "#define SJ_R " << k.rows << "\n#define SJ_F " << (k.inputs ? k.inputs : 1) << "\n#define SJ_H "
@@ -921,7 +978,7 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
                 o << " case " << n << ": it = sj_bgemm_class<" << n << ">(Ms, Ls, it, nitems, As, Bs); break;";
-        o << "\n#define SJ_PREFETCH " << (k.order == 2 ? 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n#define SJ_ACCUM 0\n";
+        o << "\n#define SJ_PREFETCH " << (k.order >= 2 ? k.order - 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n#define SJ_ACCUM 0\n";
         bgemm_common = kTpl_bgemm_common;
         body = wave_form ? kTpl_bgemm_wave : kTpl_bgemm;
         *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";

@@ -187,7 +187,7 @@ def test_bgemm_and_mlp_specs_compile(P):
 
 @pytest.mark.parametrize("kernel,bad", [
     ("SJ_BGEMM", dict(class_mask=1)), ("SJ_BGEMM", dict(unroll=3)), ("SJ_BGEMM", dict(dtype=1)),
-    ("SJ_BGEMM", dict(tile_n=-1)), ("SJ_BGEMM", dict(tile_k=2)), ("SJ_BGEMM", dict(order=3)),
+    ("SJ_BGEMM", dict(tile_n=-1)), ("SJ_BGEMM", dict(tile_k=2)), ("SJ_BGEMM", dict(order=5)),
     ("SJ_MLP_FWD", dict(dtype=3, rows=0, inputs=4, width=4)), ("SJ_MLP_FWD", dict(dtype=3, rows=4, inputs=65, width=4)),
     ("SJ_MLP_BWD", dict(dtype=0, rows=4, inputs=4, width=4)), ("SJ_ADAM", dict(dtype=3, rows=0)),
 ])
@@ -400,9 +400,11 @@ def test_scattering_specs(P):
     assert h != P.sj_specialize(P.SJ_SCATTERING, **dict(base, count=3))   # the material count is part of the key
     src = P.sj_emit_source(P.SJ_SCATTERING, **base)
     assert "#define SJ_NL 3" in src and "#define SJ_LANE_NM 1" in src and "#define SJ_SG 9" in src
-    assert "#define SJ_LANE_NM 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(base, layout="DGZ"))
-    # ZDG: threads along z by default, along nm (staged degree matrices) with order 2
-    zdg = dict(base, layout="ZDG", flags=0)
+    assert "#define SJ_LANE_NM 0" in P.sj_emit_source(P.SJ_SCATTERING, **dict(base, layout="DGZ",
+                                                                               variant=P.SJ_VAR_DIRECT))
+    # the vector-FMA structure in ZDG: threads along z by default, along nm (staged degree
+    # matrices) with order 2
+    zdg = dict(base, layout="ZDG", flags=0, variant=P.SJ_VAR_DIRECT)
     src = P.sj_emit_source(P.SJ_SCATTERING, **zdg)
     assert "#define SJ_LANE_NM 0" in src and "#define SJ_SLDS 0" in src and "#define SJ_RUN_LINES 1" in src
     assert "#define SJ_PERSIST 1" in src   # persistent waves prefetching their next 64 lines
@@ -422,9 +424,42 @@ def test_scattering_specs(P):
                         (dict(flags=co | P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG), (dict(dtype=P.SJ_BF16), P.SJ_ERR_INVALID_ARG),
                         (dict(layout=7), P.SJ_ERR_INVALID_ARG),
                         (dict(order=3), P.SJ_ERR_INVALID_ARG),
-                        (dict(layout="ZDG", Z=32768, G=32, NM=16, count=4, block=512, order=2), P.SJ_ERR_UNSUPPORTED)):
+                        (dict(layout="ZDG", Z=32768, G=32, NM=16, count=4, block=512, order=2,
+                              variant=P.SJ_VAR_DIRECT), P.SJ_ERR_UNSUPPORTED)):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_SCATTERING, **dict(base, **bad))
+        assert e.value.status == status, bad
+    # the matrix-core structure where g or z is innermost: tiles per group 1, 2 or 4 (default 2,
+    # 1 with zone blocks outer), G <= 32; the default structure there
+    mf = dict(base, layout="DZG", variant=P.SJ_VAR_MFMA)
+    h = P.sj_specialize(P.SJ_SCATTERING, **mf)
+    info = P.sj_handle_info(h)
+    assert info["kernel_name"] == "sj_scattering_mfma_dzg" and info["tile_n"] == 2 and info["block"] == 256
+    assert P.sj_specialize(P.SJ_SCATTERING, **dict(mf, variant=P.SJ_VAR_AUTO)) == h
+    zi = P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(mf, layout="ZDG")))
+    assert zi["tile_n"] == 1 and zi["block"] == 128
+    assert P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(mf, layout="ZDG", tile_n=4)))["tile_n"] == 4
+    for lay in ("DGZ", "GDZ"):
+        ci = P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(base, layout=lay)))
+        assert ci["kernel_name"] == "sj_scattering_mfma_" + lay.lower() and ci["block"] == 512, lay
+    # G above 32: the vector-FMA structure by default, the matrix cores refused
+    assert P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(base, layout="DZG", G=33)))["kernel_name"] == \
+        "sj_scattering_direct_dzg"
+    src = P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, layout="ZDG"))
+    assert "#define SJ_SNM 6" in src and "#define SJ_SZ 54" in src and "#define SJ_RT 1" in src
+    assert "#define SJ_ZMAJOR 1" in src   # ZDG: zone blocks outer by default
+    assert "#define SJ_ZMAJOR 0" in P.sj_emit_source(P.SJ_SCATTERING, **mf)
+    assert "#define SJ_ZMAJOR 1" in P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, order=2))
+    # z innermost: the column form (no LDS rows)
+    for lay in ("DGZ", "GDZ"):
+        src = P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, layout=lay))
+        assert "sj_scattering_mfma_" + lay.lower() in src and "__shared__" not in src, lay
+    for bad, status in ((dict(tile_n=3), P.SJ_ERR_INVALID_ARG), (dict(G=33), P.SJ_ERR_UNSUPPORTED),
+                        (dict(order=3), P.SJ_ERR_INVALID_ARG), (dict(layout="GZD"), P.SJ_ERR_UNSUPPORTED),
+                        (dict(layout="ZGD"), P.SJ_ERR_UNSUPPORTED),
+                        (dict(tile_k=8), P.SJ_ERR_INVALID_ARG), (dict(block=1024, tile_n=4, G=32), P.SJ_ERR_UNSUPPORTED)):
+        with pytest.raises(P.SJError) as e:
+            P.sj_specialize(P.SJ_SCATTERING, **dict(mf, **bad))
         assert e.value.status == status, bad
 
 

@@ -59,10 +59,12 @@ def run_plan(P, n, A_d, B_d, C_d, graph=False, **spec):
 
 
 @pytest.mark.parametrize("spec", [dict(), dict(tile_n=256), dict(unroll=1, block=128), dict(unroll=8, block=512),
-                                  dict(unroll=2, block=64, tile_n=1000), dict(order=1),
+                                  dict(unroll=2, block=64, tile_n=1000), dict(order=1), dict(order=3),
+                                  dict(order=4, tile_n=1024, block=512), dict(order=3, tile_n=300, block=128),
                                   dict(variant=1), dict(variant=1, unroll=1, block=64, tile_n=256),
                                   dict(variant=1, unroll=4, block=256, tile_n=1024), dict(variant=1, unroll=8, block=64)],
-                         ids=["default", "w256", "u1b128", "u8b512", "u2b64", "noprefetch",
+                         ids=["default", "w256", "u1b128", "u8b512", "u2b64", "noprefetch", "prefetch2",
+                              "prefetch3-w1024b512", "prefetch2-w300b128",
                               "wave", "wave-u1b64w256", "wave-u4b256w1024", "wave-u8b64"])
 @pytest.mark.parametrize("lohi", [(3, 16), (1, 16), (1, 4), (16, 16)], ids=["n3-16", "n1-16", "n1-4", "n16"])
 def test_bgemm_small_batches(P, orc, spec, lohi):
