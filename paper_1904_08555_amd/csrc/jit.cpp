@@ -668,6 +668,14 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (order < 1 || order > 4) return fail(SJ_ERR_INVALID_ARG, "BGEMM order must be 0 .. 4");
         if (wave_form && order != 1) return fail(SJ_ERR_INVALID_ARG, "the BGEMM wave form has no prefetch order");
         key.order = order;
+        // streamed elements: nontemporal loads and stores unless asked for ordinary ones (workgroup
+        // form; the wave form's direct-to-LDS loads and its stores keep the hint)
+        const bool ntl = wave_form || !(s->flags & SJ_FLAG_LOADS_CACHED);
+        const bool nts = wave_form || !(s->flags & SJ_FLAG_STORES_CACHED);
+        key.flags &= ~(SJ_FLAG_LOADS_CACHED | SJ_FLAG_LOADS_NONTEMPORAL | SJ_FLAG_STORES_CACHED |
+                       SJ_FLAG_STORES_NONTEMPORAL);
+        key.flags |= (ntl ? SJ_FLAG_LOADS_NONTEMPORAL : SJ_FLAG_LOADS_CACHED) |
+                     (nts ? SJ_FLAG_STORES_NONTEMPORAL : SJ_FLAG_STORES_CACHED);
         return (*out = key), SJ_OK;
     }
     return fail(SJ_ERR_UNSUPPORTED, "kernel not supported by sj_specialize");
@@ -800,10 +808,16 @@ void load_store_policy(const SpecKey &k, int *nt_load, int *nt_store)
     // (163 us vs 174 us); ordinary loads for LPlusTimes (DGZ 151 us vs 186 us nontemporal) and
     // for the direct row kernels, whose lanes read each 128-byte line in two halves (171 us vs
     // 199 us).
+    // The BF16 row form reads and writes every 128-byte line in two 64-byte halves from two
+    // instructions: with nontemporal hints the halves travel separately (measured by the HBM
+    // counters at Z=262144 G=64 D=128 NM=64: 10.2 GB read and 4.7 GB written against 8.6 and
+    // 4.3), so it takes ordinary loads and stores (BF16 2.49 ms against 2.78, BF16x3 2.41
+    // against 2.54).
     const bool direct_rows = (k.variant == SJ_VAR_MFMA && k.dtype == SJ_F64 && k.I == 1 && k.order != 2);
+    const bool bf16_rows = (k.dtype != SJ_F64 && k.I == 1);
     const bool streamed = (k.variant != SJ_VAR_DIRECT) || k.I * (k.tile_n ? k.tile_n : 1) >= 16;
-    int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !direct_rows) ? 1 : 0;
-    int nts = streamed ? 1 : 0;
+    int ntl = ((k.kernel == SJ_LTIMES || k.kernel == SJ_LTIMES_LPLUS) && streamed && !direct_rows && !bf16_rows) ? 1 : 0;
+    int nts = (streamed && !bf16_rows) ? 1 : 0;
     if (k.flags & SJ_FLAG_LOADS_CACHED) ntl = 0;
     if (k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ntl = 1;
     if (k.flags & SJ_FLAG_STORES_CACHED) nts = 0;
@@ -978,7 +992,9 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
         for (int n = 1; n <= 16; ++n)
             if (k.class_mask & (1u << n))
                 o << " case " << n << ": it = sj_bgemm_class<" << n << ">(Ms, Ls, it, nitems, As, Bs); break;";
-        o << "\n#define SJ_PREFETCH " << (k.order >= 2 ? k.order - 1 : 0) << "\n#define SJ_NT_LOAD 0\n#define SJ_NT_STORE 0\n#define SJ_ACCUM 0\n";
+        o << "\n#define SJ_PREFETCH " << (k.order >= 2 ? k.order - 1 : 0) << "\n#define SJ_NT_LOAD "
+          << ((k.flags & SJ_FLAG_LOADS_NONTEMPORAL) ? 1 : 0) << "\n#define SJ_NT_STORE "
+          << ((k.flags & SJ_FLAG_STORES_NONTEMPORAL) ? 1 : 0) << "\n#define SJ_ACCUM 0\n";
         bgemm_common = kTpl_bgemm_common;
         body = wave_form ? kTpl_bgemm_wave : kTpl_bgemm;
         *name = wave_form ? "sj_bgemm_waves" : "sj_bgemm_persistent";
