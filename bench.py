@@ -45,40 +45,52 @@ LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch;
 # both factors from a 1 GiB device copy), keyed by the SHA-1 of the emitted kernel source the counters
 # were taken on: a kernel whose source has changed since reports traffic null.  The summaries with the
-# commands are the *_hbm_counters.md and bgemm_*_counters.md files under profiles/.
+# commands are the trace-and-counter files of each workload under profiles/.
 MEASURED_TRAFFIC = {
     # Z=32768 G=32 D=96 NM=16, the tuned specializations of the six nestings:
-    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 940032251,  # sj_lplustimes_cols_mfma_zdg
-    "caf4ba83110b0c9b595ccea83e82d168fa284f15": 940778229,  # sj_lplustimes_direct_dgz
-    "2a39f0c4aac61a118f1eadf2b4dde6fcb1b97a78": 940753013,  # sj_lplustimes_direct_dzg
-    "b2de5e78eac041dbf814c28dbcc56b849164c502": 940605045,  # sj_lplustimes_direct_gdz
-    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 939739133,  # sj_lplustimes_rows_mfma_gzd
-    "e92572674af57126b26f9a13a65126eeecfa5e3b": 939749117,  # sj_lplustimes_rows_mfma_zgd
-    "aac6be0336c61377439e3d3e3634416ed9e6bae9": 939996918,  # sj_ltimes_direct_dgz
-    "eab71f4174303315d32d91274d4ae3998ebd0aa5": 939996278,  # sj_ltimes_direct_dzg
-    "11390ff2859129b666d598b3a0cfb489186094d5": 939999222,  # sj_ltimes_direct_gdz
-    "293f2f0f3e5924e34ad9e0701bddaf5e21362f38": 939734779,  # sj_ltimes_direct_zdg
+    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 940050043,  # sj_lplustimes_cols_mfma_zdg
+    "2c7c9cdf86d4b19798fa6c15aa02847f433fd9de": 940673269,  # sj_lplustimes_direct_dgz
+    "d29a392ebc2ce6e725c4dc61fcb1f8aa2e82d8b6": 940707834,  # sj_lplustimes_direct_dzg
+    "65f93956b48e02a337a9396696699e9e7050d2e6": 940395639,  # sj_lplustimes_direct_gdz
+    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 939731581,  # sj_lplustimes_rows_mfma_gzd
+    "e92572674af57126b26f9a13a65126eeecfa5e3b": 939731197,  # sj_lplustimes_rows_mfma_zgd
+    "aac6be0336c61377439e3d3e3634416ed9e6bae9": 939763195,  # sj_ltimes_direct_dgz
+    "eab71f4174303315d32d91274d4ae3998ebd0aa5": 939762427,  # sj_ltimes_direct_dzg
+    "11390ff2859129b666d598b3a0cfb489186094d5": 939998966,  # sj_ltimes_direct_gdz
+    "75437275afe268eedc0d9369dd743e8d3ff4a576": 939734395,  # sj_ltimes_direct_zdg
     "b780dade1ba9509a8d304488318c03b07830cce1": 939694844,  # sj_ltimes_rows_mfma_lds_gzd
     "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 939694844,  # sj_ltimes_rows_mfma_lds_zgd
+    # other winners of the tuning on other boxes:
+    "096450941075a7b535ec0acdc4803e93fa480056": 940753013,  # sj_lplustimes_direct_dzg
+    "5eefde36174a8c0697380a33840eb250c860eea7": 940605045,  # sj_lplustimes_direct_gdz
+    "174c646463597e8495bac025d0588a78b135b42c": 939996918,  # sj_ltimes_direct_dgz
+    "6c19c99e0e177b5af870248564a960d78c9da2a4": 939996278,  # sj_ltimes_direct_dzg
     # scattering (4 materials in zone regions, Z=32768 G=32 NM=16), default specializations:
-    "68bae0dcef15aa6a98d2d54c611f996f26be545a": 270875084,  # sj_scattering_direct_dgz
-    "7e1a3e6665d1330ed3855db7588689b8b416c008": 271485379,  # sj_scattering_direct_dzg
-    "e1fb7282b229e12092619af67a6872aaacac31a6": 270873931,  # sj_scattering_direct_gdz
     "5b273898027180bb79c395b49cf8c70e35f9030d": 270032989,  # sj_scattering_direct_gzd
-    "1d1c67261e9bcacdc663123d9634d873395b25ab": 271244613,  # sj_scattering_direct_zdg
-    "f0a893edca371ae328b11107c4a596cd243f06c2": 270058716,  # sj_scattering_direct_zgd
+    "f0a893edca371ae328b11107c4a596cd243f06c2": 270058588,  # sj_scattering_direct_zgd
+    "72b818d409165b1caf6e7b882fec2e1d87c7090f": 269172848,  # sj_scattering_mfma_dgz
+    "3b3f5766b2cce9423127a1ac1c61af4316f5e8a1": 270377301,  # sj_scattering_mfma_dzg
+    "fa7a996b5cbceafbf17b0ee3785a13d0807319f2": 269172848,  # sj_scattering_mfma_gdz
+    "f6d2343044c8bd43215bb791a188b82bc4755f23": 269865697,  # sj_scattering_mfma_zdg
     # mass operator (hex 500k elements, quad 2M elements, D=4 Q=6), default specializations:
-    "760b6364988d89ff622be6ce3a7a360bcd546ea1": 1088244849,  # sj_mass_pa_pipe_2d_d4_q6
-    "4d3e1c1b6b941ce74290c31c71bad133adf2f5e3": 1376604732,  # sj_mass_pa_pipe_3d_d4_q6
-    # BF16 LTimes, Z=262144 G=64 D=128 NM=64 (psi and phi FP32):
-    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 12885323831,  # sj_ltimes_bf16_dgz
-    "32ebd620c1345acf1aacf5689aae83faa50f619a": 13790908334,  # sj_ltimes_bf16_rows_zgd
-    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 12885784689,  # sj_ltimes_bf16w_dgz
+    "760b6364988d89ff622be6ce3a7a360bcd546ea1": 1088243185,  # sj_mass_pa_pipe_2d_d4_q6
+    "4d3e1c1b6b941ce74290c31c71bad133adf2f5e3": 1376579133,  # sj_mass_pa_pipe_3d_d4_q6
+    # fused LTimes + LPlusTimes with phi written, default specializations:
+    "b47cc03618f6aa006e91323d177850787fe8c381": 1678582454,  # sj_ltimes_lplus_direct_dgz
+    "e9d19e8787d4e62dd0a5db2177e6f9099ae04d0c": 1678588662,  # sj_ltimes_lplus_direct_dzg
+    "d47c27fd76a8582576f6f961a87ccc7b01705eeb": 1679043510,  # sj_ltimes_lplus_direct_gdz
+    "1f9227015d887b2f9f4ce3d02f7ed6244aa22694": 1679022774,  # sj_ltimes_lplus_direct_zdg
+    "7d67902c774d0d781d385cc6ee7e8c6d509e6e7c": 1678789171,  # sj_ltimes_lplus_rows_mfma_lds_gzd
+    "5c68a857e356434db2f389ea39832cb23713d504": 1678762803,  # sj_ltimes_lplus_rows_mfma_lds_zgd
+    # LTimes at Z=262144 G=64 D=128 NM=64 (BF16 forms: psi and phi FP32; FP64 forms):
+    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 12885323255,  # sj_ltimes_bf16_dgz
+    "111efaeca57317b4febbd7e1e0bcd93abbe5ee20": 12961328927,  # sj_ltimes_bf16_rows_zgd
+    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 12885924913,  # sj_ltimes_bf16w_dgz
     "064caca9d342bd247e528f7049d4fd9123058c51": 12885361654,  # sj_ltimes_bf16x3_dgz
-    "52d1df12cafaf9fec65f4f34596448a022ad7c32": 14907656065,  # sj_ltimes_bf16x3_rows_zgd
-    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 12885470774,  # sj_ltimes_bf16x3w_dgz
+    "02608d4c7c058928c9748fb885a634bc6dbe4165": 12899945401,  # sj_ltimes_bf16x3_rows_zgd
+    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 12885495542,  # sj_ltimes_bf16x3w_dgz
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
-    "2264ec0462c4d7fefb670793dce5411d5c810da1": 533994725,  # sj_bgemm_persistent
+    "c3ba1c297bdc9d6ccad6fbee12c99a6e3f992468": 533975253,  # sj_bgemm_persistent
 }
 
 
@@ -87,21 +99,21 @@ MEASURED_TRAFFIC = {
 # profiles/mfma_busy_moments_bf16_bgemm_counters.md.
 MEASURED_MFMA_BUSY = {
     # Z=32768 G=32 D=96 NM=16 (FP64 matrix cores)
-    "b780dade1ba9509a8d304488318c03b07830cce1": 0.258,  # sj_ltimes_rows_mfma_lds_gzd
-    "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 0.260,  # sj_ltimes_rows_mfma_lds_zgd
-    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 0.185,  # sj_lplustimes_rows_mfma_gzd
+    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 0.219,  # sj_lplustimes_cols_mfma_zdg
+    "6faf012bc4aa3239ccf5492f1f96d8dbd3205c72": 0.181,  # sj_lplustimes_rows_mfma_gzd
     "e92572674af57126b26f9a13a65126eeecfa5e3b": 0.182,  # sj_lplustimes_rows_mfma_zgd
-    "a72057a4a6e7a246a15903f0c958be7b7c6b376f": 0.226,  # sj_lplustimes_cols_mfma_zdg
+    "b780dade1ba9509a8d304488318c03b07830cce1": 0.261,  # sj_ltimes_rows_mfma_lds_gzd
+    "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 0.260,  # sj_ltimes_rows_mfma_lds_zgd
     # Z=262144 G=64 D=128 NM=64: FP64 column kernel, BF16 forms
-    "60467b2e08b71a9f23cd2cf2872db0e82932347b": 0.774,  # sj_ltimes_cols_mfma_dgz
-    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 0.039,  # sj_ltimes_bf16_dgz
-    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 0.053,  # sj_ltimes_bf16w_dgz
-    "32ebd620c1345acf1aacf5689aae83faa50f619a": 0.046,  # sj_ltimes_bf16_rows_zgd
-    "064caca9d342bd247e528f7049d4fd9123058c51": 0.139,  # sj_ltimes_bf16x3_dgz
-    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 0.182,  # sj_ltimes_bf16x3w_dgz
-    "52d1df12cafaf9fec65f4f34596448a022ad7c32": 0.156,  # sj_ltimes_bf16x3_rows_zgd
+    "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 0.037,  # sj_ltimes_bf16_dgz
+    "111efaeca57317b4febbd7e1e0bcd93abbe5ee20": 0.047,  # sj_ltimes_bf16_rows_zgd
+    "f6f07a961f0b57a5dea97134f5a51e5e4f71965b": 0.048,  # sj_ltimes_bf16w_dgz
+    "064caca9d342bd247e528f7049d4fd9123058c51": 0.129,  # sj_ltimes_bf16x3_dgz
+    "02608d4c7c058928c9748fb885a634bc6dbe4165": 0.162,  # sj_ltimes_bf16x3_rows_zgd
+    "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 0.175,  # sj_ltimes_bf16x3w_dgz
+    "60467b2e08b71a9f23cd2cf2872db0e82932347b": 0.766,  # sj_ltimes_cols_mfma_dgz
     # batched products, 200,000 instances n ~ U{3..16}
-    "2264ec0462c4d7fefb670793dce5411d5c810da1": 0.170,  # sj_bgemm_persistent
+    "c3ba1c297bdc9d6ccad6fbee12c99a6e3f992468": 0.169,  # sj_bgemm_persistent
 }
 
 
