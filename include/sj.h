@@ -113,7 +113,8 @@ typedef enum sj_variant {
     SJ_VAR_AUTO = 0,
     SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
     SJ_VAR_STAGED = 2,   /* rows of contiguous D (or NM) values staged through LDS */
-    SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 row kernel (D innermost) or column kernel */
+    SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 row kernel (D innermost) or column kernel;
+                            SJ_SCATTERING: FP64 tiles of one moment and 16 zones (g or z innermost) */
 } sj_variant;
 
 /* Flags. */
@@ -157,7 +158,8 @@ typedef struct sj_spec {
     int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
                                FP64 MFMA rows: 16-row tiles per wave (1..8); FP64 MFMA columns and
                                BF16: columns per lane (1, 2, 4 / 1, 4); BGEMM: window size, elements
-                               per array staged in LDS (256..7168); 0 = default */
+                               per array staged in LDS (256..7168); SJ_SCATTERING, FP64 MFMA: tiles
+                               (one moment, 16 zones) per group of loads (1, 2, 4); 0 = default */
     int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
     int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs;
                                FP64 MFMA columns: 4-deep reduction steps per group of loads in flight
@@ -172,11 +174,16 @@ typedef struct sj_spec {
                                FP64 MFMA rows (LTimes, LPlusTimes and the fused pair): 1 = each lane
                                reads its operand rows from HBM, 2 = a group's rows move as flat runs
                                through LDS (even D and NM); 0 = 2 where it fits.
-                               SJ_SCATTERING in the ZDG nesting: 0 or 1 = threads run along z (whole
-                               wave on one moment: one matrix per wave where zones of a material are
-                               contiguous), 2 = threads run along nm (several degrees per wave, the
+                               SJ_SCATTERING, FP64 MFMA (the default where g or z is innermost and
+                               G <= 32): 1 = tiles taken moments outer (a wave walks along z within a
+                               moment), 2 = zone blocks outer (the tiles in flight together take the
+                               moments of the same zones); 0 = the nesting's outer axis first (2 in
+                               ZDG, else 1).
+                               SJ_SCATTERING, DIRECT in the ZDG nesting: 0 or 1 = threads run along z
+                               (whole wave on one moment: one matrix per wave where zones of a material
+                               are contiguous), 2 = threads run along nm (several degrees per wave, the
                                material's matrices staged in LDS: faster when the material changes from
-                               zone to zone); the other nestings accept 0, 1 or 2 and ignore it */
+                               zone to zone); the other DIRECT nestings accept 0, 1 or 2 and ignore it */
     int64_t  rows, inputs, width;  /* MLP: batch rows, input features, hidden width */
 } sj_spec;
 
