@@ -985,6 +985,29 @@ def bench_small(a):
                          eager_with_lookup_us_per_launch=round(e_ms * 1e3, 3),
                          kernel=P.sj_handle_info(h)["kernel_name"])
         del g
+    # the floor: the same graph of 64 dependent launches of a one-column LTimes (one workgroup, 8 bytes
+    # of psi), i.e. what a launch costs in this graph with no data to move
+    tiny = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(3)]
+    h_t = P.sj_specialize(P.SJ_LTIMES, layout="DGZ", Z=1, G=1, D=1, NM=1)
+    P.sj_run(h_t, tiny)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(nset):
+            P.sj_run(h_t, tiny)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(max(5, a.steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        per.append((e0, e1))
+    torch.cuda.synchronize()
+    floor_us = statistics.median(x.elapsed_time(y) for x, y in per) / nset * 1e3
+    del g
     tot = res["ltimes"]["graph_us_per_launch"] + res["lplustimes"]["graph_us_per_launch"]
     line = {
         "metric": "LTimes + LPlusTimes per-launch time at the small DGZ shape (HIP graph of 64 launches)",
@@ -999,6 +1022,9 @@ def bench_small(a):
                      "frac": res["ltimes"]["graph_frac"], "traffic": None, "kernel": res["ltimes"]["kernel"],
                      "avg_us": res["ltimes"]["graph_us_per_launch"], "bytes_per_launch": nbytes},
         "per_kernel": res,
+        "launch_floor_us": round(floor_us, 3),
+        "floor_note": ("per-launch time of the same graph with a one-column LTimes: what a dependent launch "
+                       "costs here with no data to move"),
     }
     print(json.dumps(line), flush=True)
 

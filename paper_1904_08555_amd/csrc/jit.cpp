@@ -569,7 +569,8 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             const int64_t tp = 16 * ((Gv + 15) / 16) + 2;   // LDS rows where g is innermost
             if (sg == 1 && (int64_t)(key.block / 64) * rt * 16 * tp * 8 + 512 > 160 * 1024)
                 return fail(SJ_ERR_UNSUPPORTED, "scattering MFMA tiles exceed 160 KiB of LDS at this block size");
-            key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+            key.index64 = (s->G * lines >= (int64_t(1) << 31) || s->count * nl * s->G * s->G >= (int64_t(1) << 31) ||
+                        (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
             const bool xcd = (s->flags & SJ_FLAG_XCD_CONTIGUOUS) != 0;
             key.flags &= ~(SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
             key.flags |= xcd ? SJ_FLAG_XCD_CONTIGUOUS : SJ_FLAG_XCD_INTERLEAVED;
@@ -602,7 +603,8 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
         if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
         if (lds(key.block) + 512 > 160 * 1024)
             return fail(SJ_ERR_UNSUPPORTED, "scattering line tiles exceed 160 KiB of LDS at this block size");
-        key.index64 = (s->G * lines >= (int64_t(1) << 31) || (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+        key.index64 = (s->G * lines >= (int64_t(1) << 31) || s->count * nl * s->G * s->G >= (int64_t(1) << 31) ||
+                        (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
         key.order = zdg_nm ? 2 : 1;
         // workgroup order over the XCDs: explicit flag, else the hardware's round-robin order
         const bool xcd = (s->flags & SJ_FLAG_XCD_CONTIGUOUS) != 0;

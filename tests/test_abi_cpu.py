@@ -442,6 +442,12 @@ def test_scattering_specs(P):
     for lay in ("DGZ", "GDZ"):
         ci = P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(base, layout=lay)))
         assert ci["kernel_name"] == "sj_scattering_mfma_" + lay.lower() and ci["block"] == 512, lay
+    # 64-bit indexing when the matrices alone pass 2^31 elements (65536 materials x 64 degrees x 32^2),
+    # though phi is small
+    for var in (P.SJ_VAR_AUTO, P.SJ_VAR_DIRECT):
+        big = dict(base, layout="DZG", Z=16, G=32, NM=4096, count=65536, variant=var)
+        assert "typedef long long sj_index_t" in P.sj_emit_source(P.SJ_SCATTERING, **big), var
+        assert "typedef int sj_index_t" in P.sj_emit_source(P.SJ_SCATTERING, **dict(big, count=1)), var
     # G above 32: the vector-FMA structure by default, the matrix cores refused
     assert P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(base, layout="DZG", G=33)))["kernel_name"] == \
         "sj_scattering_direct_dzg"
