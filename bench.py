@@ -710,6 +710,13 @@ def bench_batched(a):
     gper, _ = flushed(generic, max(3, a.steps // 2))
     gmed = statistics.median(gper)
     info = P.sj_handle_info(h)
+    # the device-copy rate (512 MB read and written, the scratch read before each copy), the practical
+    # ceiling of a stream that reads and writes
+    csrc = torch.ones(total, dtype=torch.float64, device="cuda")
+    cdst = torch.empty_like(csrc)
+    cmed, _ = time_launches(lambda: cdst.copy_(csrc), max(5, a.steps // 2), stream, flush, warmup=2)
+    copy_gbs = 2 * total * 8 / (cmed * 1e-3) / 1e9
+    del csrc, cdst
     line = {
         "metric": "batched small products GB/s (persistent per-class graph launch vs per-instance generic)",
         "value": round(nbytes / (med * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": a.steps,
@@ -726,7 +733,11 @@ def bench_batched(a):
         "graph_us_median": round(med * 1e3, 2), "direct_launch_us_median": round(statistics.median(run_per) * 1e3, 2),
         "host_wall_ms_per_step_with_scratch_write": round(t_total * 1e3 / a.steps, 4),
         "generic_us": round(gmed * 1e3, 2),
-        "speedup_vs_generic": round(gmed / med, 3), "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
+        "speedup_vs_generic": round(gmed / med, 3),
+        "direct_launch_speedup_vs_generic": round(gmed / statistics.median(run_per), 3),
+        "measured_copy_gbs": round(copy_gbs, 1),
+        "direct_launch_frac_of_measured_copy": round(nbytes / (statistics.median(run_per) * 1e-3) / 1e9 / copy_gbs, 4),
+        "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
         "tiles": tile, "tiles_from": tuned_by, "tuned_candidates": n_tuned,
         "tune_s": None if tune_s is None else round(tune_s, 1),
         "kernel_info": {k: info[k] for k in ("vgprs", "sgprs", "occupancy", "lds_bytes", "scratch_bytes", "block",

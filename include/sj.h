@@ -114,7 +114,8 @@ typedef enum sj_variant {
     SJ_VAR_DIRECT = 1,   /* lanes along the contiguous column axis, direct HBM<->VGPR */
     SJ_VAR_STAGED = 2,   /* rows of contiguous D (or NM) values staged through LDS */
     SJ_VAR_MFMA = 3      /* matrix cores: BF16 dtypes; FP64 row kernel (D innermost) or column kernel;
-                            SJ_SCATTERING: FP64 tiles of one moment and 16 zones (g or z innermost) */
+                            SJ_SCATTERING: FP64 tiles of one moment and 16 zones (the default where
+                            g or z is innermost; with nm innermost, 16-zone blocks staged in LDS) */
 } sj_variant;
 
 /* Flags. */
@@ -158,8 +159,9 @@ typedef struct sj_spec {
     int32_t  tile_n;        /* DIRECT: columns per thread (1, 2, 4); STAGED: rows per workgroup;
                                FP64 MFMA rows: 16-row tiles per wave (1..8); FP64 MFMA columns and
                                BF16: columns per lane (1, 2, 4 / 1, 4); BGEMM: window size, elements
-                               per array staged in LDS (256..7168); SJ_SCATTERING, FP64 MFMA: tiles
-                               (one moment, 16 zones) per group of loads (1, 2, 4); 0 = default */
+                               per array staged in LDS (256..7168); SJ_SCATTERING, FP64 MFMA with g or
+                               z innermost: tiles (one moment, 16 zones) per group of loads (1, 2, 4;
+                               nm innermost takes 0 only); 0 = default */
     int32_t  tile_k;        /* STAGED: reduction values staged per step; 0 = default */
     int32_t  unroll;        /* DIRECT: reduction steps whose loads are issued before their FMAs;
                                FP64 MFMA columns: 4-deep reduction steps per group of loads in flight

@@ -140,6 +140,14 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
 // size limits) the next structure that accepts it, so that every valid shape
 // has a default.  D innermost: MFMA rows, STAGED, DIRECT; a column axis
 // innermost: DIRECT, MFMA columns.
+// LDS bytes of the nm-innermost scattering MFMA form: 16 zones x G runs of NM moments, run pitch
+// NM + 2 (NM + 1 when odd) doubles, zone pitch two doubles more than G runs
+static int64_t scattering_block_lds(int64_t NM, int64_t G)
+{
+    const int64_t nmp = NM + (NM % 2 == 0 ? 2 : 1);
+    return 16 * (G * nmp + 2) * 8;
+}
+
 sj_status make_key(sj_kernel k, const sj_spec *s, int device, const char *arch, SpecKey *out)
 {
     if (!s || !out) return fail(SJ_ERR_INVALID_ARG, "null spec or output");
@@ -550,9 +558,25 @@ static sj_status make_key_one(sj_kernel k, const sj_spec *s, int device, const c
             // FP64 matrix cores: tiles of one moment and 16 zones, tile_n tiles per group of loads,
             // persistent waves, the fragments of a matrix in registers; g innermost: the tile's
             // lines through LDS rows; z innermost: lanes along z, no LDS
-            if (sg != 1 && sz != 1)
-                return fail(SJ_ERR_UNSUPPORTED, "the scattering MFMA structure needs g or z innermost (DZG, ZDG, DGZ, GDZ)");
             if (Gv > 32) return fail(SJ_ERR_UNSUPPORTED, "the scattering MFMA structure holds G <= 32");
+            if (sg != 1 && sz != 1) {
+                // nm innermost (GZD, ZGD): blocks of 16 zones staged whole in LDS, one tile per moment
+                if (s->tile_n != 0) return fail(SJ_ERR_INVALID_ARG, "the nm-innermost MFMA form takes no tile_n");
+                if (s->order > 1) return fail(SJ_ERR_INVALID_ARG, "the nm-innermost MFMA form has order 1 only");
+                key.variant = SJ_VAR_MFMA;
+                key.tile_n = 1;
+                key.order = 1;
+                key.block = s->block ? s->block : 256;
+                if (!valid_block(key.block)) return fail(SJ_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+                if (scattering_block_lds(NMv, Gv) + 512 > 160 * 1024)
+                    return fail(SJ_ERR_UNSUPPORTED, "a 16-zone block of the nm-innermost MFMA form exceeds 160 KiB of LDS");
+                key.index64 = (s->G * lines >= (int64_t(1) << 31) || s->count * nl * s->G * s->G >= (int64_t(1) << 31) ||
+                               (s->flags & SJ_FLAG_INDEX64)) ? 1 : 0;
+                const bool xcd = (s->flags & SJ_FLAG_XCD_CONTIGUOUS) != 0;
+                key.flags &= ~(SJ_FLAG_XCD_CONTIGUOUS | SJ_FLAG_XCD_INTERLEAVED);
+                key.flags |= xcd ? SJ_FLAG_XCD_CONTIGUOUS : SJ_FLAG_XCD_INTERLEAVED;
+                return (*out = key), SJ_OK;
+            }
             // order 1: moments outer (tiles in flight together run along z); order 2: zone blocks
             // outer (tiles in flight together take the moments of the same zones); default: the
             // nesting's outer axis first
@@ -695,6 +719,12 @@ static bool scattering_pairs(const SpecKey &k)
     return nm_fastest && nl * (k.G * k.G + 2) * 8 <= 64 * 1024;
 }
 
+// scattering nestings with nm innermost (GZD, ZGD); with NM = 1 another axis is innermost too
+static bool scattering_nm_inner(const SpecKey &k)
+{
+    return (k.layout == SJ_GZD || k.layout == SJ_ZGD) && k.NM > 1;
+}
+
 // scattering with G innermost and no staged matrices (threads along z): persistent waves that
 // load their next 64 lines during the current ones (measured on MI355X at Z=32768 G=32 NM=16,
 // zone regions: DZG 66.9 us against 73.7 us, ZDG 77.7 us against 89.2 us, bit-identical)
@@ -709,7 +739,10 @@ Geometry key_geometry(const SpecKey &k)
     Geometry g{0, (unsigned)k.block, 0};
     if (k.kernel == SJ_MLP_FWD || k.kernel == SJ_MLP_BWD || k.kernel == SJ_ADAM)
         g.grid = (unsigned)((k.rows + k.block - 1) / k.block);
-    if (k.kernel == SJ_SCATTERING && k.variant == SJ_VAR_MFMA) {
+    if (k.kernel == SJ_SCATTERING && k.variant == SJ_VAR_MFMA && scattering_nm_inner(k)) {
+        g.grid = (unsigned)std::min<int64_t>((k.Z + 15) / 16, 8192);   // one 16-zone block per workgroup
+        g.persistent = 1;
+    } else if (k.kernel == SJ_SCATTERING && k.variant == SJ_VAR_MFMA) {
         const int64_t groups = (k.NM * ((k.Z + 15) / 16) + k.tile_n - 1) / k.tile_n, waves = k.block / 64;
         g.grid = (unsigned)std::min<int64_t>((groups + waves - 1) / waves, 8192);
         g.persistent = 1;
@@ -951,7 +984,8 @@ sj_status emit_source(const SpecKey &k, std::string *src, std::string *name, std
               << "\n#define SJ_BLOCK " << k.block << "\n#define SJ_NT_LOAD " << ntl
               << "\n#define SJ_NT_STORE " << nts << "\n#define SJ_ACCUM 0\n"
               << "#define SJ_XCD " << ((k.flags & SJ_FLAG_XCD_CONTIGUOUS) ? 8 : 0) << "\n" << kXcdHelper;
-            body = (sg == 1) ? kTpl_scattering_mfma_rows : kTpl_scattering_mfma_cols;
+            body = (sg == 1) ? kTpl_scattering_mfma_rows : (sz == 1) ? kTpl_scattering_mfma_cols : kTpl_scattering_mfma_blocks;
+            if (sg != 1 && sz != 1) o << "#define SJ_ZOUTER " << (sz > sg ? 1 : 0) << "\n";
             *name = std::string("sj_scattering_mfma_") + lay[k.layout];
             o << "#define SJ_KERNEL_NAME " << *name << "\n";
         } else {

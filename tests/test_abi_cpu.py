@@ -420,7 +420,7 @@ def test_scattering_specs(P):
     # order only changes ZDG: elsewhere 0, 1 and 2 give the same key
     assert len({P.sj_specialize(P.SJ_SCATTERING, **dict(base, order=o)) for o in (0, 1, 2)}) == 1
     for bad, status in ((dict(count=0), P.SJ_ERR_INVALID_ARG), (dict(G=65), P.SJ_ERR_UNSUPPORTED),
-                        (dict(variant=P.SJ_VAR_MFMA), P.SJ_ERR_UNSUPPORTED), (dict(tile_n=2), P.SJ_ERR_INVALID_ARG),
+                        (dict(variant=P.SJ_VAR_MFMA, G=33), P.SJ_ERR_UNSUPPORTED), (dict(tile_n=2), P.SJ_ERR_INVALID_ARG),
                         (dict(flags=co | P.SJ_FLAG_ACCUMULATE), P.SJ_ERR_INVALID_ARG), (dict(dtype=P.SJ_BF16), P.SJ_ERR_INVALID_ARG),
                         (dict(layout=7), P.SJ_ERR_INVALID_ARG),
                         (dict(order=3), P.SJ_ERR_INVALID_ARG),
@@ -456,13 +456,21 @@ def test_scattering_specs(P):
     assert "#define SJ_ZMAJOR 1" in src   # ZDG: zone blocks outer by default
     assert "#define SJ_ZMAJOR 0" in P.sj_emit_source(P.SJ_SCATTERING, **mf)
     assert "#define SJ_ZMAJOR 1" in P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, order=2))
+    # nm innermost: the block form on request (the vector form stays the default there)
+    for lay in ("GZD", "ZGD"):
+        assert P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(mf, layout=lay)))["kernel_name"] == \
+            "sj_scattering_mfma_" + lay.lower()
+        assert P.sj_handle_info(P.sj_specialize(P.SJ_SCATTERING, **dict(base, layout=lay)))["kernel_name"] == \
+            "sj_scattering_direct_" + lay.lower()
+        assert ("#define SJ_ZOUTER %d" % (lay == "ZGD")) in P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, layout=lay))
     # z innermost: the column form (no LDS rows)
     for lay in ("DGZ", "GDZ"):
         src = P.sj_emit_source(P.SJ_SCATTERING, **dict(mf, layout=lay))
         assert "sj_scattering_mfma_" + lay.lower() in src and "__shared__" not in src, lay
     for bad, status in ((dict(tile_n=3), P.SJ_ERR_INVALID_ARG), (dict(G=33), P.SJ_ERR_UNSUPPORTED),
-                        (dict(order=3), P.SJ_ERR_INVALID_ARG), (dict(layout="GZD"), P.SJ_ERR_UNSUPPORTED),
-                        (dict(layout="ZGD"), P.SJ_ERR_UNSUPPORTED),
+                        (dict(order=3), P.SJ_ERR_INVALID_ARG), (dict(layout="GZD", tile_n=2), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZGD", order=2), P.SJ_ERR_INVALID_ARG),
+                        (dict(layout="ZGD", G=32, NM=64), P.SJ_ERR_UNSUPPORTED),   # the 16-zone block exceeds LDS
                         (dict(tile_k=8), P.SJ_ERR_INVALID_ARG), (dict(block=1024, tile_n=4, G=32), P.SJ_ERR_UNSUPPORTED)):
         with pytest.raises(P.SJError) as e:
             P.sj_specialize(P.SJ_SCATTERING, **dict(mf, **bad))

@@ -170,7 +170,7 @@ def test_scattering_mfma_parity(P, orc, layout, shape, regions, rt, order):
     assert componentwise_err(got, ref, scale) <= TOL_F64
 
 
-@pytest.mark.parametrize("layout", MFMA_LAYOUTS)
+@pytest.mark.parametrize("layout", MFMA_LAYOUTS + ["GZD", "ZGD"])
 def test_scattering_mfma_integer_bitexact_and_bad_material(P, orc, layout):
     """Small integers: every partial sum is exact, so the matrix-core result equals the
     oracle's bit for bit; zones with an out-of-range material get NaN, the rest stay exact."""
@@ -192,7 +192,7 @@ def test_scattering_mfma_integer_bitexact_and_bad_material(P, orc, layout):
     assert np.array_equal(got[:, :, good], ref_l[:, :, good])
 
 
-@pytest.mark.parametrize("layout", MFMA_LAYOUTS)
+@pytest.mark.parametrize("layout", MFMA_LAYOUTS + ["GZD", "ZGD"])
 @pytest.mark.parametrize("regions", [True, False], ids=["regions", "random"])
 def test_scattering_mfma_full_size_sampled(P, orc, layout, regions):
     """Z=32768 G=32 NM=16, four materials: 512 sampled zones (all their lines) against the oracle."""
@@ -216,3 +216,21 @@ def test_scattering_mfma_full_size_sampled(P, orc, layout, regions):
     assert componentwise_err(got_log, ref, scale) <= TOL_F64
     del phi_d, out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("layout", ["GZD", "ZGD"])
+@pytest.mark.parametrize("shape", [(37, 5, 10, 3), (300, 3, 16, 2), (256, 32, 16, 4), (9, 4, 40, 2),
+                                   (20, 31, 7, 2), (130, 17, 4, 1), (48, 16, 5, 3), (1000, 32, 9, 4), (17, 2, 2, 2)],
+                         ids=lambda s: "Z%dG%dNM%dmat%d" % s)
+@pytest.mark.parametrize("regions", [True, False], ids=["regions", "random"])
+@pytest.mark.parametrize("block", [256, 512])
+def test_scattering_mfma_blocks_parity(P, orc, layout, shape, regions, block):
+    """nm innermost: 16-zone blocks staged whole in LDS, one tile per moment; ragged zone blocks,
+    odd NM (8-byte pieces), G not a multiple of 16, materials mixed inside a block."""
+    Z, G, NM, nmat = shape
+    S, mat, phi = scat_inputs(59, Z, G, NM, nmat, regions)
+    phi_flat = gen.to_layout(phi, layout).ravel()
+    got = run(P, layout, Z, G, NM, nmat, S, mat, phi_flat, variant=P.SJ_VAR_MFMA, block=block)
+    ref = orc.scattering(layout, Z, G, NM, S, mat, phi_flat)
+    scale = orc.scattering(layout, Z, G, NM, S, mat, phi_flat, absolute=True)
+    assert componentwise_err(got, ref, scale) <= TOL_F64
