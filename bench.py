@@ -1084,6 +1084,19 @@ def bench_scattering(a):
                         tile_n=info["tile_n"], block=info["block"], order=info.get("order"),
                         compile_ms=round(info["compile_ms"], 1), src_sha1=source_sha1(P, P.SJ_SCATTERING, spec),
                         traffic=measured_traffic(P, P.SJ_SCATTERING, spec))
+        if info["variant"] == P.SJ_VAR_DIRECT:   # the matrix-core structure of this nesting beside it, if any
+            try:
+                hm = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat,
+                                                                  variant=P.SJ_VAR_MFMA))
+            except P.SJError:
+                hm = None
+            if hm is not None:
+                tm, _ = time_launches(lambda: P.sj_run(hm, [S_d, mat_reg, phi, out]), a.steps, stream, flush,
+                                      warmup=10)
+                tmr, _ = time_launches(lambda: P.sj_run(hm, [S_d, mat_rnd, phi, out]), max(3, a.steps // 4), stream,
+                                       flush)
+                res[lay].update(mfma_us=round(tm * 1e3, 1), mfma_random_materials_us=round(tmr * 1e3, 1),
+                                mfma_kernel=P.sj_handle_info(hm)["kernel_name"])
         if info["variant"] != P.SJ_VAR_DIRECT:   # the vector-FMA structure of this nesting beside it
             hd = P.sj_specialize(P.SJ_SCATTERING, P.make_spec(layout=lay, Z=Z, G=G, NM=NM, count=nmat,
                                                               variant=P.SJ_VAR_DIRECT))
