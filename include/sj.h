@@ -342,9 +342,12 @@ sj_status sj_run_mlp_bwd_noalloc(sj_handle h, void *const *ptrs, int nptrs, void
  * untimed launches, then `reps` launches, each bracketed by HIP events on
  * `stream`.  When flush_bytes > 0 the caller's scratch buffer `flush`
  * (16-byte aligned, else SJ_ERR_ALIGN) is read in full before every timed
- * launch (outside the bracket) so the launch does not find its operands in L2
- * or the 256 MB last-level cache.  Reading, not writing: a written buffer
- * would leave dirty lines whose write-back falls into the timed launch.
+ * launch (outside the bracket, with ordinary loads, which take over the lines
+ * of L2 and of the 256 MB last-level cache) so the launch does not find its
+ * operands there.  Reading, not writing: a written buffer would leave dirty
+ * lines whose write-back falls into the timed launch.  A launch whose stores
+ * stay in the caches (ordinary stores) leaves part of its own write-back for
+ * after its end event; timing without a flush, launch after launch, counts it.
  * times_ms[reps] receives each launch's duration; the stream is synchronized
  * before returning.  Pointers as for sj_run. */
 sj_status sj_time_run(sj_handle h, void *const *ptrs, int nptrs, int warmup, int reps, void *flush,

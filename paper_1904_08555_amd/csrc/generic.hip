@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(256) flush_read(sj_u4 *p, size_t n16, size_t t
 {
     sj_u4 acc = {0u, 0u, 0u, 0u};
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
-        acc ^= __builtin_nontemporal_load(p + i);
+        acc ^= p[i];   // ordinary loads: they take the last-level cache's lines (nontemporal ones did not evict it)
     if (threadIdx.x == 0 && blockIdx.x == 0)
         for (size_t i = 0; i < tail; ++i) acc.x ^= tail_p[i];
     if (n16 > 0 && acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u && acc.z == 0xf39cc060u && acc.w == 0x5cedc834u)
