@@ -166,7 +166,7 @@ def parse():
                     help="moments: comma-separated NESTING:kernel items (e.g. GZD:ltimes); every tuner candidate of "
                          "each, with ordinary and with nontemporal stores, is timed inside the whole step")
     ap.add_argument("--picker-part", default="all", choices=("all", "collect", "evaluate"))
-    ap.add_argument("--picker-slice", default="", help="held-out shapes lo:hi for --picker-part collect")
+    ap.add_argument("--picker-slice", default="", help="held-out shapes lo:hi, or train (the training timings), for --picker-part collect")
     ap.add_argument("--picker-data", default="", help="comma-separated collect outputs for --picker-part evaluate")
     ap.add_argument("--workload", default="moments", choices=("moments", "batched", "bf16", "picker", "copy", "fused", "values", "scattering", "mass",
                              "small"),
@@ -1107,6 +1107,10 @@ def bench_scattering(a):
                             direct_kernel=P.sj_handle_info(hd)["kernel_name"],
                             speedup_vs_direct=round(td / t, 3))
     dom = max(res, key=lambda k: res[k]["us"])
+    # the device-copy rate at this size (phi to phi_out, the same scratch read before each copy): the
+    # practical ceiling of a launch that reads and writes 134 MB each
+    cmed, _ = time_launches(lambda: out.copy_(phi), max(5, a.steps // 2), stream, flush, warmup=2)
+    copy_gbs = 2 * phi.numel() * 8 / (cmed * 1e-3) / 1e9
     line = {
         "metric": "scattering source GB/s over six nestings (specialized kernels)",
         "value": round(nbytes * len(layouts) / (tot * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
@@ -1116,7 +1120,8 @@ def bench_scattering(a):
                    "layouts": layouts, "cache": "1 GiB scratch read before every timed launch"},
         "roofline": {"bound": "hbm", "achieved": res[dom]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res[dom]["frac"], "traffic": res[dom]["traffic"], "kernel": res[dom]["kernel"],
-                     "avg_us": res[dom]["us"], "bytes_per_launch": nbytes},
+                     "avg_us": res[dom]["us"], "bytes_per_launch": nbytes, "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(res[dom]["gbs"] / copy_gbs, 4)},
         "per_layout": res,
     }
     print(json.dumps(line), flush=True)
@@ -1260,25 +1265,30 @@ def bench_copy(a):
 
 
 def bench_picker(a):
-    """Learned picker against the exhaustive tuner: 250 training shapes x 8
-    random candidates = 2000 timed training configurations; 200 held-out
+    """Learned picker against the exhaustive tuner: 750 training shapes x 8
+    random candidates = 6000 timed training configurations; 200 held-out
     shapes, each timed over the tuner's whole candidate set C(s) (every
     nesting's tune.candidates); regret of the pick and of the spread-based
     shortlist against the tuner's best, compiles needed, and speedup over the
-    untuned default.  --picker-part collect (with --picker-slice lo:hi) gathers
-    timings into out-dir/picker_data_<lo>_<hi>.json, so that the collection can
-    be split over several runs; --picker-part evaluate trains and scores on the
-    files named by --picker-data."""
+    untuned default.  --picker-part collect gathers timings into
+    out-dir/picker_data_<lo>_<hi>.json for --picker-slice lo:hi (held-out
+    shapes lo..hi-1) or out-dir/picker_data_train.json for --picker-slice train,
+    so that the collection can be split over several runs; --picker-part
+    evaluate trains and scores on the files named by --picker-data."""
     from paper_1904_08555_amd import picker
 
     t0 = time.perf_counter()
     os.makedirs(a.out_dir, exist_ok=True)
     log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
-    lo, hi = (int(x) for x in a.picker_slice.split(":")) if a.picker_slice else (0, 200)
+    if a.picker_part == "collect" and a.picker_slice == "train":
+        lo, hi, train, name = 0, 0, "only", "train"
+    else:
+        lo, hi = (int(x) for x in a.picker_slice.split(":")) if a.picker_slice else (0, 200)
+        train, name = a.picker_part == "all", f"{lo}_{hi}"
     if a.picker_part in ("all", "collect"):
         data = picker.collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log=log,
-                              eval_slice=(lo, hi), train=(lo == 0))
-        path = os.path.join(a.out_dir, f"picker_data_{lo}_{hi}.json")
+                              eval_slice=(lo, hi), train=train, extra_train_shapes=500)
+        path = os.path.join(a.out_dir, f"picker_data_{name}.json")
         with open(path, "w") as f:
             json.dump(data, f)
         if a.picker_part == "collect":
@@ -1309,7 +1319,7 @@ def bench_picker(a):
         "value": res["regret_mean"], "unit": "fraction", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 model; f64 and bf16x3 kernels", "data": "synthetic (SplitMix64 + timings gathered here)",
-        "config": {"workload": "picker: 2000 timed training configs (250 shapes x 8 candidates), 200 held-out "
+        "config": {"workload": "picker: 6000 timed training configs (750 shapes x 8 candidates), 200 held-out "
                                "shapes each timed over the exhaustive tuner's candidate set; Z=k^3 k in 8..64, "
                                "G in 8..128, D in 16..256 step 8, NM in {4,9,16,36,64}, dtype in {f64, bf16x3}"},
         "roofline": None, "cpu_baseline": None, "picker": res,

@@ -383,17 +383,29 @@ def draw_shapes(rng, n, max_k=64):
     return out
 
 
+def experiment_shapes(n_train_shapes, n_eval, seed=0, max_k=64, extra_train_shapes=0):
+    """(training shapes, held-out shapes): n_train_shapes, then the n_eval
+    held-out shapes, then extra_train_shapes more training shapes, all from one
+    generator, so the held-out shapes depend only on the seed, n_train_shapes
+    and max_k."""
+    rng = np.random.default_rng(seed)
+    train_shapes = draw_shapes(rng, n_train_shapes, max_k)
+    eval_shapes = draw_shapes(rng, n_eval, max_k)
+    return train_shapes + draw_shapes(rng, extra_train_shapes, max_k), eval_shapes
+
+
 def collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log=print, max_k=64, layouts=None,
-            eval_slice=None, train=True):
+            eval_slice=None, train=True, extra_train_shapes=0):
     """Timings for the experiment: per_shape random candidates of each training
     shape, and every candidate (the exhaustive tuner's whole set) plus the
     default of each held-out shape.  ``eval_slice`` = (lo, hi) restricts the
     held-out shapes (to split a long collection over several runs); the shapes
-    themselves depend only on the seed.  Returns a JSON-able dict."""
+    themselves depend only on the seed.  ``extra_train_shapes`` more training
+    shapes are drawn after the held-out ones, so that the held-out shapes do
+    not depend on it.  ``train`` = False skips the training timings; "only"
+    times them and no held-out shape.  Returns a JSON-able dict."""
     from .farm import CompileFarm
-    rng = np.random.default_rng(seed)
-    train_shapes = draw_shapes(rng, n_train_shapes, max_k)
-    eval_shapes = draw_shapes(rng, n_eval, max_k)
+    train_shapes, eval_shapes = experiment_shapes(n_train_shapes, n_eval, seed, max_k, extra_train_shapes)
     crng = np.random.default_rng(seed + 1)
     items = []
     for s in train_shapes:
@@ -401,6 +413,8 @@ def collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log
         for j in crng.choice(len(cs), size=min(per_shape, len(cs)), replace=False):
             items.append((s, cs[int(j)]))
     lo, hi = eval_slice or (0, n_eval)
+    if train == "only":
+        lo = hi = 0
     ev_items = []
     for i in range(lo, hi):
         s = eval_shapes[i]
@@ -417,7 +431,7 @@ def collect(n_train_shapes=250, per_shape=8, n_eval=200, seed=0, workers=12, log
             out["train_collect_s"] = round(time.time() - t0, 1)
             log(f"training timings: {len(out['train'])}")
         t0 = time.time()
-        ev_times = time_items(farm, bufs, [(s, c) for _, s, c in ev_items], log=log)
+        ev_times = time_items(farm, bufs, [(s, c) for _, s, c in ev_items], log=log) if ev_items else []
         out["eval_collect_s"] = round(time.time() - t0, 1)
     rows = {}
     for (i, s, c), t in zip(ev_items, ev_times):

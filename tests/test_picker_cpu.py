@@ -63,3 +63,14 @@ def test_shortlist_follows_the_spread():
     # ties in the mean go to the lowest candidate index
     tie = _FakeEnsemble([[0.3, 0.1, 0.1]])
     assert tie.shortlist({}, [None] * 3)[0] == [1]
+
+
+def test_held_out_shapes_do_not_depend_on_extra_training_shapes():
+    key = lambda shapes: [json.dumps(s, sort_keys=True) for s in shapes]   # noqa: E731
+    tr0, ev0 = picker.experiment_shapes(250, 200, seed=0)
+    tr1, ev1 = picker.experiment_shapes(250, 200, seed=0, extra_train_shapes=500)
+    assert key(ev0) == key(ev1) and len(ev1) == 200
+    assert key(tr1[:250]) == key(tr0) and len(tr1) == 750
+    # every drawn shape respects the zone limit, and no training shape is a held-out one
+    assert all(round(s["Z"] ** (1 / 3)) <= 64 for s in tr1 + ev1)
+    assert not set(key(tr1)) & set(key(ev1))
