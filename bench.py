@@ -1312,6 +1312,7 @@ def bench_picker(a):
     res["eval_collect_s"] = sum(d.get("eval_collect_s") or 0 for d in parts)
     wall = time.perf_counter() - t0
     pk.save(os.path.join(a.out_dir, "picker_weights.json"))
+    pk.save(os.path.join(a.out_dir, "picker_weights.npz"))   # the form shipped as picker.PRETRAINED
     with open(os.path.join(a.out_dir, "picker_rows.json"), "w") as f:
         json.dump(rows, f)
     line = {

@@ -33,6 +33,7 @@ from __future__ import annotations
 
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -357,19 +358,62 @@ class Picker:
         return cands[i], pred
 
     def save(self, path):
-        with open(path, "w") as f:
-            json.dump(dict(thetas=[m.theta.cpu().numpy().tolist() for m in self.mlps], mu=self.mu.tolist(),
-                           sd=self.sd.tolist(), tsd=self.tsd, nfeat=NFEAT, width=WIDTH), f)
+        """The ensemble's parameters and feature scaling, as JSON or (path ending
+        in .npz) a numpy archive that loads without unpickling."""
+        d = dict(thetas=[m.theta.cpu().numpy().tolist() for m in self.mlps], mu=self.mu.tolist(),
+                 sd=self.sd.tolist(), tsd=self.tsd, nfeat=NFEAT, width=WIDTH)
+        if str(path).endswith(".npz"):
+            _save_npz(d, path)
+        else:
+            with open(path, "w") as f:
+                json.dump(d, f)
 
     def load(self, path):
         import torch
-        with open(path) as f:
-            d = json.load(f)
+        d = _load_weights(path)
         self.mlps = [MLP() for _ in d["thetas"]]
         for m, th in zip(self.mlps, d["thetas"]):
-            m.theta = torch.tensor(th, dtype=torch.float32, device="cuda")
+            m.theta = torch.tensor(np.asarray(th, dtype=np.float32), device="cuda")
         self.mu, self.sd = np.array(d["mu"]), np.array(d["sd"])
-        self.tsd = d["tsd"]
+        self.tsd = float(d["tsd"])
+
+    @classmethod
+    def pretrained(cls, path=None):
+        """The ensemble trained on MI355X timings (750 shapes x 8 candidates, the
+        workload of ``collect``), shipped with the package as PRETRAINED."""
+        p = cls(members=0)
+        p.load(path or PRETRAINED)
+        return p
+
+
+PRETRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "picker_mi355x.npz")
+
+
+def _save_npz(d, path):
+    np.savez(path, thetas=np.asarray(d["thetas"], dtype=np.float32), mu=np.asarray(d["mu"], dtype=np.float64),
+             sd=np.asarray(d["sd"], dtype=np.float64), tsd=np.float64(d["tsd"]), nfeat=np.int64(d["nfeat"]),
+             width=np.int64(d["width"]))
+
+
+def _load_weights(path):
+    """Saved weights as a dict, checked against this module's network size."""
+    if str(path).endswith(".npz"):
+        with np.load(path, allow_pickle=False) as z:
+            d = {k: z[k] for k in ("thetas", "mu", "sd", "tsd", "nfeat", "width")}
+    else:
+        with open(path) as f:
+            d = json.load(f)
+    nparams = WIDTH * NFEAT + WIDTH * WIDTH + 3 * WIDTH + 1
+    if int(d["nfeat"]) != NFEAT or int(d["width"]) != WIDTH or any(len(t) != nparams for t in d["thetas"]) \
+            or len(d["mu"]) != NFEAT or len(d["sd"]) != NFEAT:
+        raise ValueError(f"{path}: weights of a network with {d['nfeat']} features and width {d['width']}, "
+                         f"expected {NFEAT} and {WIDTH}")
+    return d
+
+
+def weights_to_npz(json_path, npz_path):
+    """Convert weights saved as JSON to the numpy archive form (no GPU needed)."""
+    _save_npz(_load_weights(json_path), npz_path)
 
 
 # ------------------------------------------------------------------ the experiment

@@ -102,3 +102,27 @@ def test_picker_gain_small(P):
     assert res["shortlist_regret_mean"] <= 0.15
     assert res["regret_mean"] < 0.5 * res["random_choice_regret_mean"]
     assert res["shortlist_speedup_vs_default_geomean"] > 1.0
+
+
+def test_pretrained_picker(P, orc):
+    """The ensemble shipped with the package: its predictions are the FP64
+    oracle's forward pass of the shipped weights over the standardized features
+    (within the forward bar), and its pick and shortlist come from the shape's
+    candidate set."""
+    from paper_1904_08555_amd import picker
+    pk = picker.Picker.pretrained()
+    assert len(pk.mlps) == 5
+    d = picker._load_weights(picker.PRETRAINED)
+    rng = np.random.default_rng(11)
+    for s in picker.draw_shapes(rng, 3):
+        cands = picker.candidates(s)
+        F = pk._norm(np.stack([picker.features(s, c) for c in cands]))
+        got = pk.predict_members(s, cands)
+        for k, th in enumerate(d["thetas"]):
+            ref = orc.mlp_forward(picker.NFEAT, picker.WIDTH, np.asarray(th, dtype=np.float64),
+                                  F.astype(np.float32).astype(np.float64)) * pk.tsd
+            assert np.abs(got[k] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()) * max(1.0, pk.tsd)
+        choice, _ = pk.pick(s, cands)
+        assert choice in cands
+        short, _ = pk.shortlist(s, cands)
+        assert 1 <= len(short) <= picker.KMAX and all(0 <= j < len(cands) for j in short)

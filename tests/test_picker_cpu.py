@@ -74,3 +74,29 @@ def test_held_out_shapes_do_not_depend_on_extra_training_shapes():
     # every drawn shape respects the zone limit, and no training shape is a held-out one
     assert all(round(s["Z"] ** (1 / 3)) <= 64 for s in tr1 + ev1)
     assert not set(key(tr1)) & set(key(ev1))
+
+
+def test_pretrained_weights_ship_with_the_package():
+    """The shipped ensemble loads without unpickling and matches the network the
+    module builds; a JSON round trip through the converter keeps every value."""
+    d = picker._load_weights(picker.PRETRAINED)
+    P = picker.WIDTH * picker.NFEAT + picker.WIDTH * picker.WIDTH + 3 * picker.WIDTH + 1
+    assert np.asarray(d["thetas"]).shape == (5, P) and np.isfinite(d["thetas"]).all()
+    assert np.all(np.asarray(d["sd"]) > 0) and float(d["tsd"]) > 0
+
+
+def test_weights_round_trip(tmp_path):
+    rng = np.random.default_rng(0)
+    P = picker.WIDTH * picker.NFEAT + picker.WIDTH * picker.WIDTH + 3 * picker.WIDTH + 1
+    d = dict(thetas=rng.standard_normal((2, P)).astype(np.float32).tolist(), mu=rng.standard_normal(picker.NFEAT).tolist(),
+             sd=(1 + rng.random(picker.NFEAT)).tolist(), tsd=0.7, nfeat=picker.NFEAT, width=picker.WIDTH)
+    (tmp_path / "w.json").write_text(json.dumps(d))
+    picker.weights_to_npz(str(tmp_path / "w.json"), str(tmp_path / "w.npz"))
+    back = picker._load_weights(str(tmp_path / "w.npz"))
+    assert np.array_equal(np.asarray(back["thetas"]), np.asarray(d["thetas"], dtype=np.float32))
+    assert np.array_equal(back["mu"], d["mu"]) and np.array_equal(back["sd"], d["sd"]) and float(back["tsd"]) == 0.7
+    d["width"] = 32
+    (tmp_path / "bad.json").write_text(json.dumps(d))
+    import pytest
+    with pytest.raises(ValueError):
+        picker._load_weights(str(tmp_path / "bad.json"))
