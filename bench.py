@@ -1265,8 +1265,9 @@ def bench_copy(a):
 
 
 def bench_picker(a):
-    """Learned picker against the exhaustive tuner: 750 training shapes x 8
-    random candidates = 6000 timed training configurations; 200 held-out
+    """Learned picker against the exhaustive tuner: 250 training shapes x 8
+    random candidates = 2000 timed training configurations (and, beside it,
+    the same evaluation with 500 more training shapes: 6000); 200 held-out
     shapes, each timed over the tuner's whole candidate set C(s) (every
     nesting's tune.candidates); regret of the pick and of the spread-based
     shortlist against the tuner's best, compiles needed, and speedup over the
@@ -1307,23 +1308,32 @@ def bench_picker(a):
     for d in parts:
         data["train"] += d.get("train", [])
         data["eval"] += d["eval"]
-    res, pk, rows = picker.evaluate(data, seed=0, epochs=200, log=log)
-    res["train_collect_s"] = sum(d.get("train_collect_s") or 0 for d in parts)
-    res["eval_collect_s"] = sum(d.get("eval_collect_s") or 0 for d in parts)
+    # the headline: 2000 timed training configurations (the 250 shapes drawn before the held-out
+    # ones, 8 candidates each); then the same held-out evaluation with all 6000
+    base = {json.dumps(s, sort_keys=True) for s in picker.experiment_shapes(250, 200, seed=0)[0]}
+    data_base = dict(train=[x for x in data["train"] if json.dumps(x[0], sort_keys=True) in base], eval=data["eval"])
+    res, _, rows = picker.evaluate(data_base, seed=0, epochs=200, log=log)
+    res_all, pk_all, rows_all = picker.evaluate(data, seed=0, epochs=200, log=log)
+    for r in (res, res_all):
+        r["train_collect_s"] = sum(d.get("train_collect_s") or 0 for d in parts)
+        r["eval_collect_s"] = sum(d.get("eval_collect_s") or 0 for d in parts)
     wall = time.perf_counter() - t0
-    pk.save(os.path.join(a.out_dir, "picker_weights.json"))
-    pk.save(os.path.join(a.out_dir, "picker_weights.npz"))   # the form shipped as picker.PRETRAINED
+    pk_all.save(os.path.join(a.out_dir, "picker_weights.json"))
+    pk_all.save(os.path.join(a.out_dir, "picker_weights.npz"))   # the form shipped as picker.PRETRAINED
     with open(os.path.join(a.out_dir, "picker_rows.json"), "w") as f:
         json.dump(rows, f)
+    with open(os.path.join(a.out_dir, "picker_rows_6000.json"), "w") as f:
+        json.dump(rows_all, f)
     line = {
         "metric": "picker regret vs exhaustive autotuner (mean over held-out shapes)",
         "value": res["regret_mean"], "unit": "fraction", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(wall * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 model; f64 and bf16x3 kernels", "data": "synthetic (SplitMix64 + timings gathered here)",
-        "config": {"workload": "picker: 6000 timed training configs (750 shapes x 8 candidates), 200 held-out "
+        "config": {"workload": "picker: 2000 timed training configs (250 shapes x 8 candidates), 200 held-out "
                                "shapes each timed over the exhaustive tuner's candidate set; Z=k^3 k in 8..64, "
                                "G in 8..128, D in 16..256 step 8, NM in {4,9,16,36,64}, dtype in {f64, bf16x3}"},
         "roofline": None, "cpu_baseline": None, "picker": res,
+        "picker_6000_training_configs": res_all,
     }
     print(json.dumps(line), flush=True)
 
