@@ -5,7 +5,7 @@ specialization of a shape; the picker predicts each candidate's run time
 relative to the shape's other candidates and compiles only what it cannot rule
 out.  The candidate set of a shape s is exactly the tuner's: C(s) = the union
 over nestings of tune.candidates(LTimes, nesting, s), so the tuner's best over C(s) is both
-the judge of the picker's regret and its fallback.
+the measure of the picker's regret and its fallback.
 
 Model: five networks (features -> 64 -> 64 -> 1, ReLU, FP32, different seeds);
 each is trained on the GPU with the library's own kernels (SJ_MLP_BWD for the
