@@ -709,6 +709,23 @@ def bench_batched(a):
     generic()
     gper, _ = flushed(generic, max(3, a.steps // 2))
     gmed = statistics.median(gper)
+    # the generic kernel captured in a graph of its own, so that graph replay meets graph replay
+    # (a replay costs the same fixed time over a direct launch whatever kernel it holds); its
+    # output is checked bit for bit against the direct launch's before it is timed
+    torch.cuda.synchronize()
+    c_direct = C_d.clone()
+    ggraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ggraph):
+        generic()
+    for _ in range(2):
+        C_d.zero_()
+        ggraph.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(C_d, c_direct):
+            raise RuntimeError("the graph-captured generic batched product differs from its direct launch")
+    ggper, _ = flushed(ggraph.replay, max(3, a.steps // 2))
+    ggmed = statistics.median(ggper)
+    del ggraph, c_direct
     info = P.sj_handle_info(h)
     # the device-copy rate (512 MB read and written, the scratch read before each copy), the practical
     # ceiling of a stream that reads and writes
@@ -735,6 +752,8 @@ def bench_batched(a):
         "generic_us": round(gmed * 1e3, 2),
         "speedup_vs_generic": round(gmed / med, 3),
         "direct_launch_speedup_vs_generic": round(gmed / statistics.median(run_per), 3),
+        "generic_graph_us": round(ggmed * 1e3, 2),
+        "speedup_vs_generic_graph": round(ggmed / med, 3),
         "measured_copy_gbs": round(copy_gbs, 1),
         "direct_launch_frac_of_measured_copy": round(nbytes / (statistics.median(run_per) * 1e-3) / 1e9 / copy_gbs, 4),
         "jit_ms": round(jit_ms, 1), "plan_ms": round(plan_ms, 1),
