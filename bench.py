@@ -1013,7 +1013,8 @@ def bench_small(a):
                          graph_gbs=round(nbytes / (g_ms * 1e-3) / 1e9, 1),
                          graph_frac=round(nbytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          eager_with_lookup_us_per_launch=round(e_ms * 1e3, 3),
-                         kernel=P.sj_handle_info(h)["kernel_name"])
+                         kernel=P.sj_handle_info(h)["kernel_name"], src_sha1=source_sha1(P, kid, spec),
+                         traffic=measured_traffic(P, kid, spec))
         del g
     # the floor: the same graph of 64 dependent launches of a one-column LTimes (one workgroup, 8 bytes
     # of psi), i.e. what a launch costs in this graph with no data to move
@@ -1049,7 +1050,7 @@ def bench_small(a):
                    "specialization": "exhaustive tuner" if tuned else "library defaults"},
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": res["ltimes"]["graph_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": res["ltimes"]["graph_frac"], "traffic": None, "kernel": res["ltimes"]["kernel"],
+                     "frac": res["ltimes"]["graph_frac"], "traffic": res["ltimes"]["traffic"], "kernel": res["ltimes"]["kernel"],
                      "avg_us": res["ltimes"]["graph_us_per_launch"], "bytes_per_launch": nbytes},
         "per_kernel": res,
         "launch_floor_us": round(floor_us, 3),
