@@ -100,3 +100,37 @@ def test_weights_round_trip(tmp_path):
     import pytest
     with pytest.raises(ValueError):
         picker._load_weights(str(tmp_path / "bad.json"))
+
+
+def test_evaluate_scores_regret_by_its_definition():
+    """evaluate() against hand-computed regrets: r = t(choice) / min t - 1 per shape,
+    then the mean; the shortlist keeps its fastest member; the random choice is the
+    mean regret over the whole set; the default and the speedup over it likewise."""
+    class Fixed(picker.Picker):
+        def __init__(self, table):
+            self.table = table
+
+        def predict_members(self, shape, cands):
+            return np.asarray(self.table[shape["k"]], dtype=np.float64)
+
+    rows = [
+        # shape 0: the model is sure of candidate 0 (2.0 ms), the best is candidate 1 (1.0 ms)
+        dict(shape=dict(k=0), times=[("a", 2.0), ("b", 1.0), ("c", 4.0)], default_ms=3.0),
+        # shape 1: the model cannot separate candidates 1 and 2; the shortlist times both
+        dict(shape=dict(k=1), times=[("a", 5.0), ("b", 3.0), ("c", 2.5)], default_ms=2.5),
+    ]
+    table = {0: [[0.0, 1.0, 2.0]] * 3,
+             1: [[1.0, 0.0, 0.01], [1.0, 0.02, 0.0], [1.0, 0.01, 0.02]]}
+    res, _, out = picker.evaluate(dict(eval=rows), picker=Fixed(table), log=lambda m: None)
+    pick = [2.0 / 1.0 - 1, 3.0 / 2.5 - 1]            # shape 1 picks b (mean 0.01 < 0.01 + ...)
+    short = [2.0 / 1.0 - 1, 0.0]                       # shape 1's shortlist holds c
+    rand = [np.mean([1.0, 0.0, 3.0]), np.mean([1.0, 0.2, 0.0])]
+    dflt = [3.0 / 1.0 - 1, 0.0]
+    assert [r["pick"] for r in out] == ["a", "b"] and [r["t_best"] for r in out] == [1.0, 2.5]
+    assert res["eval_shapes"] == 2 and res["compiles_mean"] == 1.5
+    assert np.isclose(res["regret_mean"], np.mean(pick), atol=1e-4)
+    assert np.isclose(res["shortlist_regret_mean"], np.mean(short), atol=1e-4)
+    assert np.isclose(res["random_choice_regret_mean"], np.mean(rand), atol=1e-4)
+    assert np.isclose(res["default_regret_mean"], np.mean(dflt), atol=1e-4)
+    assert np.isclose(res["speedup_vs_default_geomean"], np.sqrt(3.0 / 2.0 * 2.5 / 3.0), atol=1e-4)
+    assert res["within_10pct"] == 0.0 and res["shortlist_within_10pct"] == 0.5
