@@ -40,13 +40,6 @@ sys.path.insert(0, ROOT)
 METRIC = "LTimes GB/s & %roofline: JIT-specialized vs generic kernel; JIT ms; picker regret"
 HBM_PEAK_GBS = 8000.0
 LAYOUTS = ("DGZ", "DZG", "GDZ", "GZD", "ZDG", "ZGD")
-# The order of the six nesting pairs in the timed step.  Each LTimes stores phi with ordinary stores,
-# so the previous pair's phi is still dirty in the last-level cache and is written back while the
-# next LTimes runs; which kernel absorbs that write-back depends on the sequence.  Measured on MI355X
-# (three repeats of four orders, Z=32768 G=32 D=96 NM=16): this order's step is 1.0-2.0% shorter than
-# the order of LAYOUTS, where the GZD LTimes after the GDZ pair took 182-183 us against 170-172 us
-# in every other position tried.
-STEP_ORDER = ("DGZ", "GZD", "DZG", "ZGD", "ZDG", "GDZ")
 
 
 # HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch;
@@ -157,8 +150,7 @@ def parse():
     ap.add_argument("--G", type=int, default=32)
     ap.add_argument("--D", type=int, default=96)
     ap.add_argument("--NM", type=int, default=16)
-    ap.add_argument("--layouts", default="", help="comma-separated nestings (default: all six; the step "
-                                                   "runs them in STEP_ORDER)")
+    ap.add_argument("--layouts", default="", help="comma-separated nestings (default: all six, in the order of LAYOUTS)")
     ap.add_argument("--no-generic", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU baseline sample")
@@ -227,7 +219,7 @@ def bench_moments(a):
     from sj_inputs import device as gdev
 
     Z, G, D, NM = a.Z, a.G, a.D, a.NM
-    layouts = [x for x in a.layouts.split(",") if x] or list(STEP_ORDER)
+    layouts = [x for x in a.layouts.split(",") if x] or list(LAYOUTS)
     tile = {}
     for kv in filter(None, a.tile.split(",")):
         k, v = kv.split("=")
