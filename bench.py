@@ -91,6 +91,17 @@ MEASURED_TRAFFIC = {
     "11d9a11b89c49eb5977c1f64152ffa1996085ad5": 12885495542,  # sj_ltimes_bf16x3w_dgz
     # batched products, 200,000 instances n ~ U{3..16}, default specialization:
     "c3ba1c297bdc9d6ccad6fbee12c99a6e3f992468": 533975253,  # sj_bgemm_persistent
+    # Z=32768 G=32 D=96 NM=16, another tuned set of the six nestings (the LDS-staged row LTimes with
+    # two row tiles per wave, rotation and workgroups on contiguous XCD ranges):
+    "caf4ba83110b0c9b595ccea83e82d168fa284f15": 940723317,  # sj_lplustimes_direct_dgz (read 134.7 MB, written 806.0 MB)
+    "b5f2c3a8fd909fd198ad33fa9fcc6bf107e645fa": 940802293,  # sj_lplustimes_direct_dzg (read 134.7 MB, written 806.1 MB)
+    "17fd69e3b29440e0f912deb3add2f6c1d8336777": 940737525,  # sj_lplustimes_direct_gdz (read 134.7 MB, written 806.0 MB)
+    "57160d60ee27647a4376d637645887fbcdf2dc84": 940342136,  # sj_lplustimes_direct_zdg (read 134.6 MB, written 805.8 MB)
+    "c9ee1470bfb94602eb0ea22725114c770abea167": 939964157,  # sj_lplustimes_rows_mfma_zgd (read 134.3 MB, written 805.6 MB)
+    "4536cc7cb047bfe2cc8fe4196b61564ef4249a63": 939732731,  # sj_ltimes_direct_dgz (read 805.5 MB, written 134.2 MB)
+    "133d138961c05fb37623878b4f19d58e5f256ae1": 939995126,  # sj_ltimes_direct_dzg (read 805.8 MB, written 134.2 MB)
+    "f9e011450da5ffd5c729f1fc92560b93116f25d1": 939694844,  # sj_ltimes_rows_mfma_lds_gzd (read 805.5 MB, written 134.2 MB)
+    "39f562d0cb6361bc8681a427185ee496c7bbf708": 939694844,  # sj_ltimes_rows_mfma_lds_zgd (read 805.5 MB, written 134.2 MB)
 }
 
 
