@@ -115,6 +115,10 @@ MEASURED_MFMA_BUSY = {
     "e92572674af57126b26f9a13a65126eeecfa5e3b": 0.182,  # sj_lplustimes_rows_mfma_zgd
     "b780dade1ba9509a8d304488318c03b07830cce1": 0.261,  # sj_ltimes_rows_mfma_lds_gzd
     "2c35009ddb2bddd0e9acd536270cc3e2c19c0777": 0.260,  # sj_ltimes_rows_mfma_lds_zgd
+    # the same shape, the second tuned set (two row tiles per wave, rotation, contiguous XCD ranges)
+    "f9e011450da5ffd5c729f1fc92560b93116f25d1": 0.262,  # sj_ltimes_rows_mfma_lds_gzd
+    "39f562d0cb6361bc8681a427185ee496c7bbf708": 0.259,  # sj_ltimes_rows_mfma_lds_zgd
+    "c9ee1470bfb94602eb0ea22725114c770abea167": 0.222,  # sj_lplustimes_rows_mfma_zgd
     # Z=262144 G=64 D=128 NM=64: FP64 column kernel, BF16 forms
     "1d98ee3ef25cf25ec41313284a3c5dd1789a6681": 0.037,  # sj_ltimes_bf16_dgz
     "111efaeca57317b4febbd7e1e0bcd93abbe5ee20": 0.047,  # sj_ltimes_bf16_rows_zgd
